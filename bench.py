@@ -1,0 +1,212 @@
+"""Benchmark of the Ahmad-Cohen regular-force step on one MI355X.
+
+Workload: the million-body cluster -- N = 2^20 Plummer sphere, Kroupa (2001)
+IMF, 5% of bodies in primordial binaries, Hermite step levels 2^-3..2^-20 --
+at its full block (all N bodies active), the shape of the paper's
+million-body runs (section 4.2, section 5).  One step = predict all N bodies
+to the block time + regular force, jerk and neighbour lists of the full block
+(nb_cap 1024).  Inputs are generated on the host and resident in HBM before
+timing starts.
+
+Printed: ONE JSON line with the mixed-precision pair-interaction rate as
+`value` (G pairs/s), the FP64 rate beside it, the dominant kernel's roofline
+(ALU-bound: algorithmic flops per pair x pairs / kernel time, timed with HIP
+events on the library's stream), the per-level aggregate, and the CPU oracle
+timed on a bounded row sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point operations per regular pair interaction
+# (acc + jerk, FMA counted as 2): r = xj - xi (3), u = vj - vi (3), r.r (5),
+# r.u (5), 1/sqrt (1), r^-2 (1), m r^-3 (2), 3 (r.u) r^-2 (2), acc += m r^-3 r
+# (6), jerk += m r^-3 (u - alpha r) (12).
+FLOPS_PER_PAIR = 39
+# MI355X published vector peaks (TFLOP/s): FP32 157.3 (with packed FP32
+# instructions), FP64 78.6.  256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz =
+# 78.6 TFLOP/s is also the ceiling of unpacked FP32.
+PEAK_FP32 = 157.3
+PEAK_FP64 = 78.6
+PEAK_UNPACKED = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--cpu-rows", type=int, default=4096,
+                    help="rows of the full block timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--no-levels", action="store_true")
+    ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1504_03687_amd as nb
+    import workloads as W
+
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    t_gen = time.time()
+    s = W.config3(args.n)
+    n = s["n"]
+    t, t0, blk = W.config3_level(s, 3)
+    log(f"workload generated in {time.time() - t_gen:.1f}s: n={n} full block={blk.size}")
+    x, v, a, jk, m = dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(s["m"])
+    t0d, ibd, rs2d = dev(t0), dev(blk), dev(s["rs2"][blk])
+    cap = s["nb_cap"]
+    n_i = blk.size
+    pairs = float(n_i) * float(n - 1)
+    xp = torch.empty_like(x)
+    vp = torch.empty_like(v)
+    out = (torch.empty((3, n_i), dtype=torch.float64, device="cuda"),
+           torch.empty((3, n_i), dtype=torch.float64, device="cuda"),
+           torch.empty(n_i, dtype=torch.int32, device="cuda"),
+           torch.empty((n_i, cap), dtype=torch.int32, device="cuda"),
+           torch.empty(1, dtype=torch.int32, device="cuda"))
+    ctx = nb.Context(0)
+
+    def step(prec):
+        nb.predict(x, v, a, jk, t0d, t, out=(xp, vp), ctx=ctx)
+        nb.regular_force(xp, vp, m, ibd, rs2d, cap, prec, out=out, ctx=ctx)
+
+    res = {}
+    precs = ["mixed", "fp64"] if args.only == "both" else [args.only]
+    for prec in precs:
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        ctx.reset_timing()
+        ctx.enable_timing(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step(prec)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        kms, kl = ctx.kernel_time(nb.CLASS_FORCE)
+        mms, ml = ctx.kernel_time(nb.CLASS_MERGE)
+        pms, pl = ctx.kernel_time(nb.CLASS_PREDICT)
+        ctx.enable_timing(False)
+        ms_step = (t2 - t1) * 1e3 / args.steps
+        res[prec] = dict(ms_per_step=ms_step, pairs_per_s=pairs / (ms_step * 1e-3),
+                         force_kernel_ms=kms / max(kl, 1), merge_kernel_ms=mms / max(ml, 1),
+                         predict_kernel_ms=pms / max(pl, 1), plan=ctx.last_plan(),
+                         overflow=int(out[4].item()))
+        log(f"{prec}: {ms_step:.2f} ms/step, {pairs / ms_step * 1e-6:.1f} G pairs/s, "
+            f"force kernel {res[prec]['force_kernel_ms']:.2f} ms, plan {ctx.last_plan()}")
+
+    # per-level blocks of the step hierarchy (occurrence-weighted aggregate)
+    levels = None
+    if not args.no_levels:
+        levels = {}
+        tot_pairs = {p: 0.0 for p in precs}
+        tot_time = {p: 0.0 for p in precs}
+        for L in range(3, 21):
+            tl, t0l, bl = W.config3_level(s, L)
+            if bl.size == 0:
+                continue
+            w = W.level_weight(L)
+            bd, rd, t0ld = dev(bl), dev(s["rs2"][bl]), dev(t0l)
+            ent = {"n_i": int(bl.size), "weight": w}
+            for prec in precs:
+                nb.predict(x, v, a, jk, t0ld, tl, out=(xp, vp), ctx=ctx)
+                nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
+                torch.cuda.synchronize()
+                reps = 3
+                c1 = time.perf_counter()
+                for _ in range(reps):
+                    nb.predict(x, v, a, jk, t0ld, tl, out=(xp, vp), ctx=ctx)
+                    nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - c1) * 1e3 / reps
+                p = float(bl.size) * (n - 1)
+                ent[prec] = {"ms": round(ms, 4), "gpairs_per_s": round(p / ms * 1e-6, 2)}
+                tot_pairs[prec] += w * p
+                tot_time[prec] += w * ms
+            levels[str(L)] = ent
+            log(f"level {L}: n_i={bl.size} " + " ".join(
+                f"{pp}={ent[pp]['gpairs_per_s']} G/s" for pp in precs))
+        levels["aggregate_gpairs_per_s"] = {
+            p: round(tot_pairs[p] / tot_time[p] * 1e-6, 2) for p in precs}
+
+    # CPU oracle on a bounded sample of the same full block
+    cpu = None
+    if args.cpu_rows > 0:
+        import oracle
+        rng = np.random.default_rng(0)
+        rows = rng.choice(n_i, min(args.cpu_rows, n_i), replace=False)
+        ox, ov = oracle.predict(t, s["x"], s["v"], s["a"], s["jk"], t0)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        c1 = time.perf_counter()
+        oracle.regular(ox, ov, s["m"], blk[rows], s["rs2"][blk][rows], cap)
+        dt = time.perf_counter() - c1
+        cpu = {"value": round(rows.size * (n - 1) / dt * 1e-9, 4), "unit": "G pairs/s",
+               "cores": threads, "kind": "oracle",
+               "sample": f"{rows.size} random rows of the N=2^20 full block against all "
+                         f"{n} bodies ({rows.size * (n - 1):.3g} pairs, {dt:.1f}s, FP64)"}
+        log(f"cpu oracle: {cpu['value']} G pairs/s on {threads} threads")
+
+    head = res.get("mixed") or res["fp64"]
+    dom = "mixed" if "mixed" in res else "fp64"
+    kernel_s = res[dom]["force_kernel_ms"] * 1e-3
+    achieved = FLOPS_PER_PAIR * pairs / kernel_s * 1e-12
+    peak = PEAK_FP32 if dom == "mixed" else PEAK_FP64
+    line = {
+        "metric": "regular force+jerk pair interactions/s (G/s) & % VALU peak, N=2^20, "
+                  "mixed vs FP64",
+        "value": round(head["pairs_per_s"] * 1e-9, 3),
+        "unit": "G pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if dom == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "N=2^20 Plummer + Kroupa IMF, 5% primordial binaries, full "
+                               "block (all bodies active), predict + regular force, nb_cap 1024",
+                   "n": n, "n_i": n_i, "pairs_per_step": pairs},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": f"force_rows_kernel ({dom})",
+                     "flops_per_pair": FLOPS_PER_PAIR,
+                     "frac_of_unpacked_fp32_fp64_peak": round(achieved / PEAK_UNPACKED, 4)},
+        "cpu_baseline": cpu,
+        "precisions": {p: {"gpairs_per_s": round(r["pairs_per_s"] * 1e-9, 3),
+                           "ms_per_step": round(r["ms_per_step"], 3),
+                           "force_kernel_ms": round(r["force_kernel_ms"], 3),
+                           "merge_kernel_ms": round(r["merge_kernel_ms"], 3),
+                           "predict_kernel_ms": round(r["predict_kernel_ms"], 4),
+                           "plan": r["plan"], "overflow": r["overflow"]}
+                       for p, r in res.items()},
+        "levels": levels,
+    }
+    if "mixed" in res and "fp64" in res:
+        line["mixed_over_fp64"] = round(res["mixed"]["pairs_per_s"] / res["fp64"]["pairs_per_s"], 3)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

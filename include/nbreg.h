@@ -1,0 +1,187 @@
+/*
+ * nbreg.h -- C ABI of the MI355X (gfx950) Ahmad-Cohen regular-force library.
+ *
+ * The library computes, for an active block of bodies, the regular force (the
+ * Newtonian acceleration from every body OUTSIDE the body's neighbour radius,
+ * G = 1, no softening) together with its first time derivative (jerk), and
+ * builds the neighbour list (the bodies INSIDE the radius) in the same pass.
+ * This is the Ahmad-Cohen split of Wang et al. 2015 (NBODY6++GPU), section 2,
+ * and the GPU regular-force step of section 3.2.1 (Table 1, "Reg."); the
+ * all-particle Hermite prediction that feeds it is Table 1 "Pred." and
+ * section 3.3.3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers are DEVICE pointers owned by the caller unless a name ends in
+ *    _host.  Nothing is copied to or from the host except where stated.
+ *  - Body state is structure-of-arrays FP64: a "[3][n] plane" array holds
+ *    component k of body j at element k*n + j.  Per-row outputs are [3][n_i]
+ *    planes with the same convention (plane stride n_i).
+ *  - Every call is asynchronous on the context's stream and returns before
+ *    the GPU work finishes; read outputs after synchronising that stream.
+ *    Growing the context's scratch memory may synchronise the device.
+ *  - Return value: NB_OK (0) or a negative NB_ERR_* code.  Host-checkable
+ *    argument errors are reported this way and launch nothing.  Nothing throws
+ *    across the ABI.
+ *  - Device-detected conditions are reported in the optional 'status' word
+ *    (bit-or of NB_STATUS_*; the library ORs bits in, it never clears them, so
+ *    the caller zeroes it) and, for list overflow, in the 'overflow' word
+ *    (written 0 or 1 by the call itself).
+ *  - A neighbour is decided by one canonical single-precision test, the same
+ *    in every kernel and precision: with dx = x_j - x_i in FP64 (likewise dy,
+ *    dz), fx = (float)dx, r2f = fmaf(fz, fz, fmaf(fy, fy, fx * fx)), body j
+ *    (j != i) is a neighbour of row b iff r2f < (float)rs2[b].  Equality is
+ *    regular.  rs2[b] <= 0 means "no neighbours".  The self pair is excluded.
+ *  - Neighbour lists are in ascending body index.  A row with more than nb_cap
+ *    neighbours keeps its first nb_cap (in ascending order); nb_count holds the
+ *    true count and 'overflow' is set.  Forces never depend on nb_cap.
+ */
+#ifndef NBREG_H
+#define NBREG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nb_ctx nb_ctx;
+
+typedef enum { NB_FP64 = 0, NB_MIXED = 1 } nb_precision;
+
+enum {
+    NB_OK = 0,
+    NB_ERR_INVALID_ARG = -1, /* bad size, NULL required pointer, bad enum      */
+    NB_ERR_HIP = -2,         /* a HIP runtime call failed                      */
+    NB_ERR_OOM = -3,         /* scratch could not be grown (or exceeds limit)  */
+    NB_ERR_UNSUPPORTED = -4  /* no gfx950 device, or an unsupported plan       */
+};
+
+enum {
+    NB_STATUS_OVERFLOW = 1,  /* some row has more neighbours than nb_cap       */
+    NB_STATUS_BAD_INDEX = 2, /* some i_block entry outside [0, n); row zeroed  */
+    NB_STATUS_NONFINITE = 4  /* some output is Inf/NaN (e.g. coincident bodies */
+                             /* outside each other's radius)                   */
+};
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on HIP device 'device' that launches on 'hip_stream'
+ * (a hipStream_t; NULL = the default stream).  Fails with NB_ERR_UNSUPPORTED
+ * if the device is not gfx950. */
+int nb_ctx_create(nb_ctx **out, int device, void *hip_stream);
+/* Changes the stream later calls launch on. */
+int nb_ctx_set_stream(nb_ctx *ctx, void *hip_stream);
+/* Frees scratch, cached graphs and events.  Synchronises the stream first. */
+int nb_ctx_destroy(nb_ctx *ctx);
+const char *nb_error_string(int code);
+int nb_version(void);
+
+/* Plan override used by tests and the autotuner: 0 in a field means "choose
+ * automatically".  mapping: 1 = one row per lane with j-tiles in LDS,
+ * 2 = one row per wavefront with j spread over lanes (small blocks).
+ * rows_per_lane: 1, 2 or 4 (mapping 1).  splits: number of contiguous j
+ * ranges whose partial sums are combined in FP64 (>= 1).  The override holds
+ * until changed; pass all zeros to go back to automatic plans. */
+int nb_ctx_set_plan(nb_ctx *ctx, int mapping, int rows_per_lane, int splits);
+/* Describes the plan of the last nb_regular_force call into buf (text). */
+int nb_ctx_last_plan(nb_ctx *ctx, char *buf, int len);
+/* Upper bound on scratch bytes the context may hold (0 = no bound). */
+int nb_ctx_set_scratch_limit(nb_ctx *ctx, int64_t bytes);
+
+/* Kernel timing: when enabled, every launch of the library's force kernels is
+ * bracketed by HIP events on the context's stream.  nb_ctx_kernel_time
+ * synchronises those events and returns the summed milliseconds and the
+ * launch count of one kernel class since the last reset (class 0 = regular
+ * force main kernel, 1 = cross-split reduce, 2 = predictor, 3 = adjoint,
+ * 4 = batched). */
+int nb_ctx_enable_timing(nb_ctx *ctx, int on);
+int nb_ctx_kernel_time(nb_ctx *ctx, int kernel_class, double *ms, int64_t *launches);
+int nb_ctx_reset_timing(nb_ctx *ctx);
+
+/* ---- hot path ----------------------------------------------------------- */
+
+/* Hermite predictor of all n bodies to block time t (section 3.3.3: every
+ * body is predicted once for the regular force; the force and its first
+ * derivative from the body's last step drive the prediction, section 2):
+ *   dt = t - t0[j];  xp = x + v dt + a dt^2/2 + jrk dt^3/6;
+ *   vp = v + a dt + jrk dt^2/2,
+ * evaluated in FP64 in the fixed Horner order
+ *   xp = fma(dt, fma(dt, fma(dt, jrk*C6, a*0.5), v), x),
+ *   vp = fma(dt, fma(dt, jrk*0.5, a), v),  C6 = FP64 nearest 1/6,
+ * so results are bit-reproducible.  x, v, a, jrk, xp, vp: [3][n] planes;
+ * t0: [n].  m and m32 are optional (both NULL, or both set): m32[j] =
+ * (float)m[j].  In-place (xp == x, vp == v) is allowed. */
+int nb_predict(nb_ctx *ctx, int64_t n, double t, const double *x, const double *v,
+               const double *a, const double *jrk, const double *t0, const double *m,
+               double *xp, double *vp, float *m32);
+
+/* Regular force + jerk + neighbour lists (section 2, section 3.2.1).
+ * j-set: all n bodies, predicted positions xp and velocities vp ([3][n]
+ * planes) and masses m ([n]).  Rows b = 0 .. n_i-1 are bodies i_block[b]
+ * with squared neighbour radius rs2[b]; duplicate rows are allowed and are
+ * computed independently.  For row b with i = i_block[b]:
+ *   acc_b  = sum_{j regular} m_j r / |r|^3,
+ *   jerk_b = sum_{j regular} m_j [ u / |r|^3 - 3 (r.u) r / |r|^5 ],
+ * r = xp_j - xp_i, u = vp_j - vp_i, regular = not a neighbour and j != i.
+ * prec = NB_FP64: all arithmetic in FP64.  prec = NB_MIXED: differences in
+ * FP64, then r^-1 (hardware reciprocal square root), r^-2, r^-3 and the force
+ * and jerk products in FP32, summed in short FP32 runs folded into FP64
+ * running sums, with FP64 cross-split reduction.
+ * Outputs: acc, jerk [3][n_i] FP64; nb_count [n_i] (true count); nb_list
+ * [n_i][nb_cap] row-major (first min(count, nb_cap) entries of a row are
+ * defined); *overflow (required) = 1 iff some count > nb_cap, else 0;
+ * status (optional) gets NB_STATUS_* bits.  A row whose i_block entry is
+ * outside [0, n) gets zero acc/jerk, count 0 and NB_STATUS_BAD_INDEX.
+ * Errors: n <= 0 or n > INT32_MAX, n_i < 0, nb_cap < 0, NULL required
+ * pointer (nb_list may be NULL only when nb_cap == 0), bad prec.
+ * n_i == 0 is valid and only clears *overflow. */
+int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                     const double *m, int32_t n_i, const int32_t *i_block,
+                     const double *rs2, int32_t nb_cap, nb_precision prec, double *acc,
+                     double *jerk, int32_t *nb_count, int32_t *nb_list, int32_t *overflow,
+                     uint32_t *status);
+
+/* Adjoint of nb_regular_force (no counterpart in the paper): given upstream
+ * weights w_a, w_j ([3][n_i] FP64), the gradient of
+ *   L = sum_b w_a[:,b] . acc_b + w_j[:,b] . jerk_b
+ * with respect to xp, vp ([3][n] planes) and m ([n]), with neighbour
+ * membership frozen (the canonical test at the given xp decides membership
+ * and is treated as constant).  FP64 throughout; pair terms are recomputed,
+ * nothing per pair is stored.  gx, gv, gm are overwritten (bodies in no
+ * regular pair get 0).  Same argument rules as nb_regular_force. */
+int nb_regular_force_adjoint(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                             const double *m, int32_t n_i, const int32_t *i_block,
+                             const double *rs2, const double *w_a, const double *w_j,
+                             double *gx, double *gv, double *gm, uint32_t *status);
+
+/* Batched ensemble: n_clusters independent clusters in one launch.  Cluster
+ * c owns bodies [j_off_host[c], j_off_host[c+1]) of the concatenated xp, vp,
+ * m arrays (planes of length n_total = j_off_host[n_clusters]) and rows
+ * [i_off_host[c], i_off_host[c+1]) of i_block/rs2/outputs (n_rows =
+ * i_off_host[n_clusters]).  Body indices in i_block and in nb_list are
+ * GLOBAL indices into the concatenated arrays; a row's j-set is its own
+ * cluster only.  The work of all clusters runs in one persistent kernel that
+ * pulls (cluster, row-tile, j-range) items from a queue; the launch sequence
+ * for a given shape is captured once into a HIP graph and replayed.
+ * Offsets are host arrays of n_clusters+1 int64, non-decreasing, starting
+ * at 0.  Outputs and rules as nb_regular_force. */
+int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const int64_t *j_off_host,
+                             const int64_t *i_off_host, const double *xp,
+                             const double *vp, const double *m, const int32_t *i_block,
+                             const double *rs2, int32_t nb_cap, nb_precision prec,
+                             double *acc, double *jerk, int32_t *nb_count,
+                             int32_t *nb_list, int32_t *overflow, uint32_t *status);
+
+/* Autotuner: times the candidate plans (rows per lane, splits, mapping) on
+ * synthetic Plummer-like data for a ladder of block sizes at the given n,
+ * for both precisions, and stores the fastest per (precision, n bucket, n_i
+ * bucket).  If cache_path names a readable file written by an earlier run,
+ * the table is loaded from it instead (flags & 1 forces re-tuning); after
+ * tuning the table is written there.  Synchronises the device. */
+int nb_autotune(nb_ctx *ctx, int64_t n, const char *cache_path, int flags);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBREG_H */

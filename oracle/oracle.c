@@ -365,9 +365,9 @@ double or_local_loss(int64_t n, const double *xp, const double *vp, const double
             A[kk] = w_a[(int64_t)kk * n_i + b];
             B[kk] = w_j[(int64_t)kk * n_i + b];
         }
-        for (int64_t j = 0; j < n; ++j) {
-            if (i != body && j != body)
-                continue;
+        /* only pairs that involve body: all j when it is the row body, else j = body */
+        int64_t j_lo = i == body ? 0 : body, j_hi = i == body ? n : body + 1;
+        for (int64_t j = j_lo; j < j_hi; ++j) {
             if (!member_regular(n, xm, i, j, rs2f))
                 continue;
             double r[3], u[3];

@@ -1,0 +1,351 @@
+"""MI355X (gfx950) Ahmad-Cohen regular force: Python binding of libnbreg.
+
+Thin ctypes marshalling over the C ABI declared in ``include/nbreg.h``: every
+step of the computation runs in the library's HIP kernels; PyTorch only
+provides device memory and the stream.  If the library is missing this module
+raises on first use -- there is no CPU fallback.
+
+Arrays follow the ABI's structure-of-arrays layout: positions/velocities are
+float64 tensors of shape (3, n) on the GPU, per-row outputs (3, n_i).
+
+Physics: Wang et al. 2015 (NBODY6++GPU), section 2 (Ahmad-Cohen split of the
+force into a regular part from bodies outside the neighbour radius and an
+irregular part from neighbours), section 3.2.1 (regular force, its derivative
+and the neighbour lists on the GPU in one pass) and section 3.3.3 (all-body
+prediction for the regular force).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import torch
+
+__all__ = [
+    "NbError", "Context", "lib", "library_path", "context", "predict", "regular_force",
+    "regular_force_adjoint", "regular_force_batched", "autotune", "RegularForce",
+    "FP64", "MIXED", "STATUS_OVERFLOW", "STATUS_BAD_INDEX", "STATUS_NONFINITE",
+]
+
+FP64, MIXED = 0, 1
+STATUS_OVERFLOW, STATUS_BAD_INDEX, STATUS_NONFINITE = 1, 2, 4
+CLASS_FORCE, CLASS_MERGE, CLASS_PREDICT, CLASS_ADJOINT, CLASS_BATCHED = range(5)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libnbreg.so")
+_lib = None
+_lock = threading.Lock()
+
+
+class NbError(RuntimeError):
+    """A negative return code from libnbreg."""
+
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {lib().nb_error_string(code).decode()} ({code})")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib() -> C.CDLL:
+    """Loads libnbreg.so (built by ``python -m paper_1504_03687_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"libnbreg.so not found at {_LIB_PATH}; build it with "
+                              "`python -m paper_1504_03687_amd.build`")
+        L = C.CDLL(_LIB_PATH)
+        vp, i64, i32, dbl, u32p = C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_void_p
+        sig = {
+            "nb_version": ([], C.c_int),
+            "nb_error_string": ([C.c_int], C.c_char_p),
+            "nb_ctx_create": ([C.POINTER(vp), C.c_int, vp], C.c_int),
+            "nb_ctx_set_stream": ([vp, vp], C.c_int),
+            "nb_ctx_destroy": ([vp], C.c_int),
+            "nb_ctx_set_plan": ([vp, C.c_int, C.c_int, C.c_int], C.c_int),
+            "nb_ctx_last_plan": ([vp, C.c_char_p, C.c_int], C.c_int),
+            "nb_ctx_set_scratch_limit": ([vp, i64], C.c_int),
+            "nb_ctx_enable_timing": ([vp, C.c_int], C.c_int),
+            "nb_ctx_kernel_time": ([vp, C.c_int, C.POINTER(dbl), C.POINTER(i64)], C.c_int),
+            "nb_ctx_reset_timing": ([vp], C.c_int),
+            "nb_predict": ([vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+            "nb_regular_force": ([vp, i64, vp, vp, vp, i32, vp, vp, i32, C.c_int, vp, vp, vp,
+                                  vp, vp, u32p], C.c_int),
+            "nb_regular_force_adjoint": ([vp, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
+                                          u32p], C.c_int),
+            "nb_regular_force_batched": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, i32, C.c_int, vp,
+                                          vp, vp, vp, vp, u32p], C.c_int),
+            "nb_autotune": ([vp, i64, C.c_char_p, C.c_int], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+        return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise NbError(rc, what)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, name, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Context:
+    """One libnbreg context on one device.  Calls launch on torch's current
+    stream of that device at the time of the call."""
+
+    def __init__(self, device: int | None = None):
+        L = lib()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = C.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(L.nb_ctx_create(C.byref(h), self.device, C.c_void_p(stream)), "nb_ctx_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().nb_ctx_set_stream(self._h, C.c_void_p(s)), "nb_ctx_set_stream")
+
+    def set_plan(self, mapping: int = 0, rows_per_lane: int = 0, splits: int = 0):
+        _check(lib().nb_ctx_set_plan(self._h, mapping, rows_per_lane, splits), "nb_ctx_set_plan")
+
+    def last_plan(self) -> str:
+        buf = C.create_string_buffer(256)
+        _check(lib().nb_ctx_last_plan(self._h, buf, 256), "nb_ctx_last_plan")
+        return buf.value.decode()
+
+    def set_scratch_limit(self, nbytes: int):
+        _check(lib().nb_ctx_set_scratch_limit(self._h, int(nbytes)), "nb_ctx_set_scratch_limit")
+
+    def enable_timing(self, on: bool = True):
+        _check(lib().nb_ctx_enable_timing(self._h, int(bool(on))), "nb_ctx_enable_timing")
+
+    def kernel_time(self, cls: int):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().nb_ctx_kernel_time(self._h, cls, C.byref(ms), C.byref(n)),
+               "nb_ctx_kernel_time")
+        return ms.value, n.value
+
+    def reset_timing(self):
+        _check(lib().nb_ctx_reset_timing(self._h), "nb_ctx_reset_timing")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().nb_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_ctxs: dict[int, Context] = {}
+
+
+def context(device: int | None = None) -> Context:
+    """The shared per-device context used by the module-level functions."""
+    if device is None:
+        device = torch.cuda.current_device()
+    ctx = _ctxs.get(device)
+    if ctx is None:
+        ctx = _ctxs[device] = Context(device)
+    return ctx
+
+
+def _prec(precision) -> int:
+    if precision in (FP64, "fp64", "f64", "double"):
+        return FP64
+    if precision in (MIXED, "mixed", "fp32", "mp"):
+        return MIXED
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+def predict(x, v, a, jk, t0, t: float, m=None, out=None, ctx: Context | None = None):
+    """Hermite predictor of all bodies to time t (FP64).  Returns (xp, vp, m32);
+    m32 is None unless m is given."""
+    n = t0.shape[0] if isinstance(t0, torch.Tensor) else 0
+    for name, arr in (("x", x), ("v", v), ("a", a), ("jk", jk)):
+        _dev(arr, name, torch.float64, (3, n))
+    _dev(t0, "t0", torch.float64, (n,))
+    ctx = ctx or context(x.device.index)
+    if out is None:
+        xp = torch.empty_like(x)
+        vp = torch.empty_like(v)
+    else:
+        xp, vp = out
+        _dev(xp, "xp", torch.float64, (3, n))
+        _dev(vp, "vp", torch.float64, (3, n))
+    m32 = None
+    if m is not None:
+        _dev(m, "m", torch.float64, (n,))
+        m32 = torch.empty(n, dtype=torch.float32, device=x.device)
+    ctx._bind_stream()
+    _check(lib().nb_predict(ctx.handle, n, float(t), _ptr(x), _ptr(v), _ptr(a), _ptr(jk),
+                            _ptr(t0), _ptr(m), _ptr(xp), _ptr(vp), _ptr(m32)), "nb_predict")
+    return xp, vp, m32
+
+
+def regular_force(xp, vp, m, i_block, rs2, nb_cap: int, precision="fp64", status=None,
+                  out=None, ctx: Context | None = None):
+    """Regular acc, jerk (3, n_i) float64, nb_count (n_i,) int32, nb_list
+    (n_i, nb_cap) int32 and overflow (1,) int32 -- all on the GPU, no sync."""
+    n = m.shape[0]
+    _dev(xp, "xp", torch.float64, (3, n))
+    _dev(vp, "vp", torch.float64, (3, n))
+    _dev(m, "m", torch.float64, (n,))
+    n_i = i_block.shape[0]
+    _dev(i_block, "i_block", torch.int32, (n_i,))
+    _dev(rs2, "rs2", torch.float64, (n_i,))
+    if nb_cap < 0:
+        raise ValueError("nb_cap must be >= 0")
+    dev = xp.device
+    if out is None:
+        acc = torch.empty((3, n_i), dtype=torch.float64, device=dev)
+        jerk = torch.empty((3, n_i), dtype=torch.float64, device=dev)
+        cnt = torch.empty(n_i, dtype=torch.int32, device=dev)
+        lst = torch.empty((n_i, nb_cap), dtype=torch.int32, device=dev)
+        ovf = torch.empty(1, dtype=torch.int32, device=dev)
+    else:
+        acc, jerk, cnt, lst, ovf = out
+    if status is not None:
+        _dev(status, "status", torch.int32, (1,))
+    ctx = ctx or context(dev.index)
+    ctx._bind_stream()
+    _check(lib().nb_regular_force(ctx.handle, n, _ptr(xp), _ptr(vp), _ptr(m), n_i,
+                                  _ptr(i_block), _ptr(rs2), int(nb_cap), _prec(precision),
+                                  _ptr(acc), _ptr(jerk), _ptr(cnt),
+                                  _ptr(lst) if nb_cap > 0 else None, _ptr(ovf), _ptr(status)),
+           "nb_regular_force")
+    return acc, jerk, cnt, lst, ovf
+
+
+def regular_force_adjoint(xp, vp, m, i_block, rs2, w_a, w_j, status=None,
+                          ctx: Context | None = None):
+    """dL/dxp, dL/dvp (3, n) and dL/dm (n,) for L = sum(w_a*acc + w_j*jerk),
+    neighbour membership frozen."""
+    n = m.shape[0]
+    n_i = i_block.shape[0]
+    _dev(xp, "xp", torch.float64, (3, n))
+    _dev(vp, "vp", torch.float64, (3, n))
+    _dev(m, "m", torch.float64, (n,))
+    _dev(i_block, "i_block", torch.int32, (n_i,))
+    _dev(rs2, "rs2", torch.float64, (n_i,))
+    _dev(w_a, "w_a", torch.float64, (3, n_i))
+    _dev(w_j, "w_j", torch.float64, (3, n_i))
+    if status is not None:
+        _dev(status, "status", torch.int32, (1,))
+    gx = torch.empty_like(xp)
+    gv = torch.empty_like(vp)
+    gm = torch.empty_like(m)
+    ctx = ctx or context(xp.device.index)
+    ctx._bind_stream()
+    _check(lib().nb_regular_force_adjoint(ctx.handle, n, _ptr(xp), _ptr(vp), _ptr(m), n_i,
+                                          _ptr(i_block), _ptr(rs2), _ptr(w_a), _ptr(w_j),
+                                          _ptr(gx), _ptr(gv), _ptr(gm), _ptr(status)),
+           "nb_regular_force_adjoint")
+    return gx, gv, gm
+
+
+def regular_force_batched(j_off, i_off, xp, vp, m, i_block, rs2, nb_cap: int,
+                          precision="mixed", status=None, out=None, ctx: Context | None = None):
+    """Batched ensemble (see nbreg.h).  j_off, i_off: host int64 sequences of
+    length n_clusters + 1.  Returns (acc, jerk, nb_count, nb_list, overflow)."""
+    import numpy as np
+    j_off = np.ascontiguousarray(j_off, dtype=np.int64)
+    i_off = np.ascontiguousarray(i_off, dtype=np.int64)
+    if j_off.shape != i_off.shape or j_off.ndim != 1 or j_off.size < 1:
+        raise ValueError("j_off and i_off must be 1-D of equal length n_clusters + 1")
+    n = m.shape[0]
+    n_rows = i_block.shape[0]
+    _dev(xp, "xp", torch.float64, (3, n))
+    _dev(vp, "vp", torch.float64, (3, n))
+    _dev(m, "m", torch.float64, (n,))
+    _dev(i_block, "i_block", torch.int32, (n_rows,))
+    _dev(rs2, "rs2", torch.float64, (n_rows,))
+    dev = xp.device
+    if out is None:
+        acc = torch.empty((3, n_rows), dtype=torch.float64, device=dev)
+        jerk = torch.empty((3, n_rows), dtype=torch.float64, device=dev)
+        cnt = torch.empty(n_rows, dtype=torch.int32, device=dev)
+        lst = torch.empty((n_rows, nb_cap), dtype=torch.int32, device=dev)
+        ovf = torch.empty(1, dtype=torch.int32, device=dev)
+    else:
+        acc, jerk, cnt, lst, ovf = out
+    if status is not None:
+        _dev(status, "status", torch.int32, (1,))
+    ctx = ctx or context(dev.index)
+    ctx._bind_stream()
+    _check(lib().nb_regular_force_batched(
+        ctx.handle, j_off.size - 1, j_off.ctypes.data_as(C.c_void_p),
+        i_off.ctypes.data_as(C.c_void_p), _ptr(xp), _ptr(vp), _ptr(m), _ptr(i_block),
+        _ptr(rs2), int(nb_cap), _prec(precision), _ptr(acc), _ptr(jerk), _ptr(cnt),
+        _ptr(lst) if nb_cap > 0 else None, _ptr(ovf), _ptr(status)),
+        "nb_regular_force_batched")
+    return acc, jerk, cnt, lst, ovf
+
+
+def autotune(n: int, cache_path: str | None = None, force: bool = False,
+             ctx: Context | None = None):
+    """Times candidate plans at n bodies and installs the fastest per block
+    size bucket (see nb_autotune)."""
+    ctx = ctx or context()
+    ctx._bind_stream()
+    _check(lib().nb_autotune(ctx.handle, int(n),
+                             cache_path.encode() if cache_path else None, int(bool(force))),
+           "nb_autotune")
+
+
+class RegularForce(torch.autograd.Function):
+    """(acc, jerk) = regular force of the block, differentiable with respect
+    to xp, vp and m through the library's adjoint kernels (membership frozen)."""
+
+    @staticmethod
+    def forward(ctx, xp, vp, m, i_block, rs2, nb_cap, precision="fp64"):
+        acc, jerk, cnt, lst, ovf = regular_force(xp, vp, m, i_block, rs2, nb_cap, precision)
+        ctx.save_for_backward(xp, vp, m, i_block, rs2)
+        ctx.mark_non_differentiable(cnt, lst, ovf)
+        return acc, jerk, cnt, lst, ovf
+
+    @staticmethod
+    def backward(ctx, g_acc, g_jerk, *unused):
+        xp, vp, m, i_block, rs2 = ctx.saved_tensors
+        n_i = i_block.shape[0]
+        z = torch.zeros((3, n_i), dtype=torch.float64, device=xp.device)
+        w_a = z if g_acc is None else g_acc.contiguous()
+        w_j = z if g_jerk is None else g_jerk.contiguous()
+        gx, gv, gm = regular_force_adjoint(xp, vp, m, i_block, rs2, w_a, w_j)
+        return gx, gv, gm, None, None, None, None

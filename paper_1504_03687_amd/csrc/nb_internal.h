@@ -1,0 +1,126 @@
+// Internal declarations shared by the HIP translation units of libnbreg.
+// Not part of the public ABI (that is include/nbreg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nb {
+
+// Work-group shape of every force kernel: 256 lanes = 4 wave64s.
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+// j bodies staged per LDS tile by the row-per-lane kernel.
+constexpr int kTile = 256;
+// Mixed precision: FP32 partial sums run over this many j before they are
+// folded into the FP64 running sums.
+constexpr int kFold = 32;
+// Capacity of one split's neighbour segment in scratch.  A segment that
+// overflows is rebuilt by the merge kernel from its j-range.
+constexpr int kSegCap = 96;
+
+// Position used for padding bodies in a partial LDS tile / past the end of a
+// j-range: far away (finite in FP32 after the FP64 difference), mass 0, so the
+// pair adds exactly zero and never passes the neighbour test.
+constexpr double kFar = 1.0e18;
+
+// Status bits (mirrors include/nbreg.h).
+constexpr uint32_t kStOverflow = 1u, kStBadIndex = 2u, kStNonFinite = 4u;
+
+// A contiguous range of j-set bodies [j_begin, j_end) and the rows that see it.
+struct ForceArgs {
+    int64_t n;            // bodies in the whole concatenated arrays (plane stride)
+    const double *xp;     // [3][n]
+    const double *vp;     // [3][n]
+    const double *m;      // [n]
+    int32_t n_i;          // rows (plane stride of per-row arrays)
+    const int32_t *i_block;
+    const double *rs2;
+    int32_t cap;          // caller's nb_cap
+    // final outputs (used directly when splits == 1)
+    double *acc, *jerk;   // [3][n_i]
+    int32_t *nb_count, *nb_list;
+    int32_t *overflow;
+    uint32_t *status;
+    // split layout: split s covers j in [s * split_len, min(n, (s+1) * split_len))
+    int32_t splits;
+    int64_t split_len;
+    // scratch (splits > 1): part [splits][6][n_i], seg_cnt [splits][n_i],
+    // seg_list [splits][n_i][kSegCap]
+    double *part;
+    int32_t *seg_cnt;
+    int32_t *seg_list;
+};
+
+struct Plan {
+    int mapping;        // 1 = row per lane (LDS j-tiles), 2 = row group per wave
+    int rows_per_lane;  // mapping 1: 1, 2, 4;  mapping 2: rows per wave 1, 2, 4
+    int splits;         // j-ranges (mapping 1: per work-group; mapping 2: per wave)
+};
+
+// Scratch bytes needed for a plan (0 when splits == 1).
+size_t force_scratch_bytes(const Plan &p, int32_t n_i);
+// Carves the scratch pointers of 'a' out of 'base'.
+void force_bind_scratch(ForceArgs &a, void *base);
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_force(const Plan &p, bool mixed, const ForceArgs &a, hipStream_t s);
+hipError_t launch_merge(bool mixed, const ForceArgs &a, hipStream_t s);
+hipError_t launch_predict(int64_t n, double t, const double *x, const double *v,
+                          const double *a, const double *jrk, const double *t0,
+                          const double *m, double *xp, double *vp, float *m32,
+                          hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
+
+// Adjoint: two recompute passes.
+struct AdjointArgs {
+    int64_t n;
+    const double *xp, *vp, *m;
+    int32_t n_i;
+    const int32_t *i_block;
+    const double *rs2;
+    const double *w_a, *w_j;  // [3][n_i]
+    double *gx, *gv, *gm;     // [3][n], [n]
+    uint32_t *status;
+    double *row_part;         // scratch [6][n_i]: per-row "-" terms (set by the launcher)
+};
+size_t adjoint_scratch_bytes(int64_t n, int32_t n_i, int row_splits, int body_splits);
+hipError_t launch_adjoint_plan(const AdjointArgs &a, int row_splits, int body_splits,
+                               void *scratch, hipStream_t s);
+
+// Batched ensemble.
+struct BatchItem {
+    int32_t row_begin, row_end;   // rows [row_begin, row_end)
+    int64_t j_begin, j_end;       // j-range of this item (inside its cluster)
+    int32_t slot;                 // split index of this item within its rows
+    int32_t n_slots;              // total splits of this item's rows
+};
+struct BatchArgs {
+    int64_t n;
+    const double *xp, *vp, *m;
+    int32_t n_rows;
+    const int32_t *i_block;
+    const double *rs2;
+    int32_t cap;
+    double *acc, *jerk;
+    int32_t *nb_count, *nb_list, *overflow;
+    uint32_t *status;
+    const BatchItem *items;   // device array
+    int32_t n_items;
+    int32_t *queue;           // device counter (zeroed before launch)
+    // per-row split bookkeeping: row r's slot s partial lives at
+    // part[(row_slot_base[r] + s) * 6 + k]
+    const int32_t *row_nslots;     // [n_rows]
+    const int64_t *row_slot_base;  // [n_rows]
+    const int64_t *row_j_begin;    // [n_rows] cluster j-range of the row
+    const int64_t *row_j_end;
+    const int64_t *row_split_len;  // [n_rows]
+    double *part;                  // [total_slots][6]
+    int32_t *seg_cnt;              // [total_slots]
+    int32_t *seg_list;             // [total_slots][kSegCap]
+};
+hipError_t launch_batched(bool mixed, int grid, const BatchArgs &a, hipStream_t s);
+hipError_t launch_batched_merge(bool mixed, const BatchArgs &a, hipStream_t s);
+
+}  // namespace nb

@@ -1,0 +1,153 @@
+// Device-side pair arithmetic shared by the force, merge, batched and adjoint
+// kernels of libnbreg (gfx950).
+//
+// Physics (Wang et al. 2015, section 2; fourth-order Hermite with the
+// Ahmad-Cohen neighbour scheme): for a row body i and a source body j with
+// r = x_j - x_i, u = v_j - v_i (G = 1, no softening) the regular force term is
+// m_j r / |r|^3 and its time derivative m_j [u / |r|^3 - 3 (r.u) r / |r|^5].
+// j is a neighbour of i (and contributes nothing to the regular force) iff it
+// lies inside i's neighbour radius, decided by one canonical single-precision
+// test shared by every kernel so that lists are bit-identical across kernels,
+// precisions and plans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nb {
+
+// Canonical squared distance for the neighbour test: each FP64 difference is
+// rounded to FP32 (round-to-nearest-even), then r2f = fz*fz + (fy*fy + fx*fx)
+// with two fused multiply-adds.  The whole file is compiled without
+// floating-point contraction, so the plain product fx*fx stays a product.
+__device__ __forceinline__ float canon_r2f(double dx, double dy, double dz)
+{
+    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+    return __builtin_fmaf(fz, fz, __builtin_fmaf(fy, fy, fx * fx));
+}
+
+// 1/sqrt(r2) in FP64: hardware estimate, then one third-order correction
+// y <- y (1 + e/2 + 3 e^2 / 8) with e = 1 - r2 y^2 (the Taylor series of
+// (1 - e)^-1/2).  From an estimate good to ~2^-22 this lands within an ulp or
+// two.  r2 = 0 gives NaN, which the callers mask by selection.
+__device__ __forceinline__ double rsqrt_f64(double r2)
+{
+    double y = __builtin_amdgcn_rsq(r2);
+    const double t = r2 * y;
+    const double e = __builtin_fma(-t, y, 1.0);
+    const double c = __builtin_fma(0.375, e, 0.5);
+    return __builtin_fma(y * e, c, y);
+}
+
+// Running sums of one row.  FP64 plan: FP64 sums.  Mixed plan: FP32 partial
+// sums over short runs of j, folded into FP64 running sums.
+template <bool MIXED>
+struct Sums;
+
+template <>
+struct Sums<false> {
+    double ax, ay, az, jx, jy, jz;
+    __device__ __forceinline__ void zero() { ax = ay = az = jx = jy = jz = 0.0; }
+    __device__ __forceinline__ void fold() {}
+};
+
+template <>
+struct Sums<true> {
+    double ax, ay, az, jx, jy, jz;
+    float pax, pay, paz, pjx, pjy, pjz;
+    __device__ __forceinline__ void zero()
+    {
+        ax = ay = az = jx = jy = jz = 0.0;
+        pax = pay = paz = pjx = pjy = pjz = 0.0f;
+    }
+    __device__ __forceinline__ void fold()
+    {
+        ax += (double)pax; ay += (double)pay; az += (double)paz;
+        jx += (double)pjx; jy += (double)pjy; jz += (double)pjz;
+        pax = pay = paz = pjx = pjy = pjz = 0.0f;
+    }
+};
+
+// FP64 regular term.  r2 is the FP64 squared distance; 'excl' marks the self
+// pair or a neighbour (the term is then exactly zero: r^-1 is selected to 0).
+__device__ __forceinline__ void accum_f64(Sums<false> &S, double dx, double dy, double dz,
+                                          double r2, double ux, double uy, double uz,
+                                          double mj, bool excl)
+{
+    double y = rsqrt_f64(r2);
+    y = excl ? 0.0 : y;
+    const double y2 = y * y;
+    const double mr3 = (mj * y) * y2;               // m / r^3
+    const double s = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
+    const double q = (s * y2) * (-3.0 * mr3);       // -3 m (r.u) / r^5
+    S.ax = __builtin_fma(mr3, dx, S.ax);
+    S.ay = __builtin_fma(mr3, dy, S.ay);
+    S.az = __builtin_fma(mr3, dz, S.az);
+    S.jx = __builtin_fma(q, dx, __builtin_fma(mr3, ux, S.jx));
+    S.jy = __builtin_fma(q, dy, __builtin_fma(mr3, uy, S.jy));
+    S.jz = __builtin_fma(q, dz, __builtin_fma(mr3, uz, S.jz));
+}
+
+// Mixed regular term: FP32 arithmetic on the FP32-rounded FP64 differences.
+__device__ __forceinline__ void accum_mixed(Sums<true> &S, float fx, float fy, float fz,
+                                            float r2f, double ux, double uy, double uz,
+                                            float mj, bool excl)
+{
+    const float gx = (float)ux, gy = (float)uy, gz = (float)uz;
+    float y = __builtin_amdgcn_rsqf(r2f);
+    y = excl ? 0.0f : y;
+    const float y2 = y * y;
+    const float mr3 = (mj * y) * y2;
+    const float s = __builtin_fmaf(fz, gz, __builtin_fmaf(fy, gy, fx * gx));
+    const float q = (s * y2) * (-3.0f * mr3);
+    S.pax = __builtin_fmaf(mr3, fx, S.pax);
+    S.pay = __builtin_fmaf(mr3, fy, S.pay);
+    S.paz = __builtin_fmaf(mr3, fz, S.paz);
+    S.pjx = __builtin_fmaf(q, fx, __builtin_fmaf(mr3, gx, S.pjx));
+    S.pjy = __builtin_fmaf(q, fy, __builtin_fmaf(mr3, gy, S.pjy));
+    S.pjz = __builtin_fmaf(q, fz, __builtin_fmaf(mr3, gz, S.pjz));
+}
+
+// Candidate bound for the FP64 plans: every canonical neighbour (and the self
+// pair, r2 = 0) has FP64 r2 < hi, so the exact canonical test only runs for
+// the rare pairs below hi.  The FP32 roundings in r2f change r2 by less than
+// 3.3e-7 relative; the margin 2^-20 (9.5e-7) covers that.
+__device__ __forceinline__ double cand_bound_f64(float rs2f)
+{
+    const double h = (double)rs2f * (1.0 + 0x1p-20);
+    return h > 1e-300 ? h : 1e-300;
+}
+
+// Candidate bound for the mixed plans, on r2f itself: the neighbour bound, or
+// the smallest normal float when rs2 <= 0 so that the self pair still enters.
+__device__ __forceinline__ float cand_bound_f32(float rs2f)
+{
+    return rs2f > 1.17549435e-38f ? rs2f : 1.17549435e-38f;
+}
+
+// Keeps the compiler from hoisting the rare exact-test path above its branch
+// (the test is cheap enough that it would otherwise be evaluated for every
+// pair).  Emits no instruction.
+__device__ __forceinline__ void opaque(double &a, double &b, double &c)
+{
+    __asm__ volatile("" : "+v"(a), "+v"(b), "+v"(c));
+}
+__device__ __forceinline__ void opaque(int32_t &a)
+{
+    __asm__ volatile("" : "+v"(a));
+}
+
+__device__ __forceinline__ bool finite6(double a, double b, double c, double d, double e,
+                                        double f)
+{
+    return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c) &&
+           __builtin_isfinite(d) && __builtin_isfinite(e) && __builtin_isfinite(f);
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+}  // namespace nb

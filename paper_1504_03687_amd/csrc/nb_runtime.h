@@ -1,0 +1,65 @@
+// Host-side context of libnbreg (internal; the public ABI is include/nbreg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <tuple>
+#include <vector>
+
+#include "../../include/nbreg.h"
+#include "nb_internal.h"
+
+enum {
+    NB_CLASS_FORCE = 0,
+    NB_CLASS_MERGE = 1,
+    NB_CLASS_PREDICT = 2,
+    NB_CLASS_ADJOINT = 3,
+    NB_CLASS_BATCHED = 4,
+    NB_NCLASS = 5
+};
+
+namespace nbrt {
+struct PendingTiming {
+    int cls;
+    hipEvent_t start, stop;
+};
+struct BatchedCache;   // defined in nb_batched.hip
+void batched_release(nb_ctx *ctx);
+}  // namespace nbrt
+
+struct nb_ctx {
+    int device = -1;
+    bool usable = false;   // false: host-only context (argument checks only)
+    int cu_count = 0;
+    hipStream_t stream = nullptr;
+    hipError_t last_hip_error = hipSuccess;
+    // scratch
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    size_t scratch_limit = 0;
+    // plan control
+    nb::Plan forced{};
+    bool has_forced = false;
+    char last_plan[256] = "none";
+    std::map<std::tuple<int, int64_t, int64_t>, nb::Plan> tuned;
+    // timing
+    bool timing = false;
+    std::vector<nbrt::PendingTiming> pending;
+    std::vector<hipEvent_t> free_events;
+    double ms[NB_NCLASS] = {0, 0, 0, 0, 0};
+    int64_t launches[NB_NCLASS] = {0, 0, 0, 0, 0};
+    // batched entry point: cached device metadata and graphs per shape
+    std::vector<nbrt::BatchedCache *> batched;
+};
+
+namespace nbrt {
+int hip_fail(nb_ctx *ctx, hipError_t e);
+int ensure_scratch(nb_ctx *ctx, size_t bytes);
+hipError_t timed_begin(nb_ctx *ctx, int cls, hipEvent_t *ev);
+hipError_t timed_end(nb_ctx *ctx, int cls, hipEvent_t *ev);
+int64_t bucket_log2(int64_t v);
+nb::Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed);
+void finish_plan(nb::Plan &p, int64_t n, int32_t n_i, int64_t *split_len);
+}  // namespace nbrt

@@ -1,0 +1,417 @@
+// Host runtime and C ABI of libnbreg (see include/nbreg.h for the contract).
+//
+// The context owns only its scratch memory (grown on demand, bounded by a
+// limit), timing events, the autotuned plan table and the cached HIP graphs of
+// the batched entry point.  Every entry point validates its arguments on the
+// host, picks a plan and enqueues kernels on the context's stream; nothing
+// synchronises except nb_autotune, nb_ctx_kernel_time and nb_ctx_destroy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/nbreg.h"
+#include "nb_internal.h"
+#include "nb_runtime.h"
+
+using nb::Plan;
+
+// ---------------------------------------------------------------------------
+// context helpers
+// ---------------------------------------------------------------------------
+namespace nbrt {
+
+int hip_fail(nb_ctx *ctx, hipError_t e)
+{
+    if (ctx) ctx->last_hip_error = e;
+    return NB_ERR_HIP;
+}
+
+int ensure_scratch(nb_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->scratch_bytes) return NB_OK;
+    if (ctx->scratch_limit && bytes > ctx->scratch_limit) return NB_ERR_OOM;
+    if (ctx->scratch) {
+        // the old buffer may still be in use by queued work on the stream
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e);
+        (void)hipFree(ctx->scratch);
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    want = (want + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+    if (ctx->scratch_limit && want > ctx->scratch_limit) want = bytes;
+    hipError_t e = hipMalloc(&ctx->scratch, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->scratch = nullptr;
+        return NB_ERR_OOM;
+    }
+    ctx->scratch_bytes = want;
+    return NB_OK;
+}
+
+hipError_t timed_begin(nb_ctx *ctx, int cls, hipEvent_t *ev)
+{
+    ev[0] = ev[1] = nullptr;
+    if (!ctx->timing) return hipSuccess;
+    for (int k = 0; k < 2; ++k) {
+        if (!ctx->free_events.empty()) {
+            ev[k] = ctx->free_events.back();
+            ctx->free_events.pop_back();
+        } else {
+            hipError_t e = hipEventCreate(&ev[k]);
+            if (e != hipSuccess) return e;
+        }
+    }
+    (void)cls;
+    return hipEventRecord(ev[0], ctx->stream);
+}
+
+hipError_t timed_end(nb_ctx *ctx, int cls, hipEvent_t *ev)
+{
+    if (!ctx->timing || !ev[0]) return hipSuccess;
+    hipError_t e = hipEventRecord(ev[1], ctx->stream);
+    if (e != hipSuccess) return e;
+    ctx->pending.push_back({cls, ev[0], ev[1]});
+    return hipSuccess;
+}
+
+int64_t bucket_log2(int64_t v)
+{
+    int64_t b = 0;
+    while ((int64_t(1) << (b + 1)) <= v) ++b;
+    return b;
+}
+
+// Automatic plan for a block of n_i rows against n bodies.
+Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed)
+{
+    auto it = ctx->tuned.find(std::make_tuple((int)mixed, bucket_log2(n), bucket_log2(n_i)));
+    if (it != ctx->tuned.end()) return it->second;
+    Plan p{};
+    const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
+    if (n_i < 128) {
+        p.mapping = 2;
+        p.rows_per_lane = n_i >= 4 ? 4 : (n_i >= 2 ? 2 : 1);
+        const int64_t groups = (n_i + p.rows_per_lane - 1) / p.rows_per_lane;
+        const int64_t target = (int64_t)cus * 16;   // ~4 waves per SIMD
+        int64_t s = (target + groups - 1) / groups;
+        const int64_t max_s = std::max<int64_t>(1, n / (4 * nb::kWave));
+        p.splits = (int)std::max<int64_t>(1, std::min(s, max_s));
+    } else {
+        p.mapping = 1;
+        p.rows_per_lane = n_i >= (1 << 18) ? 2 : 1;
+        const int64_t wgs = (n_i + p.rows_per_lane * nb::kBlock - 1) / (p.rows_per_lane * nb::kBlock);
+        const int64_t target = (int64_t)cus * 8;
+        int64_t s = (target + wgs - 1) / wgs;
+        const int64_t max_s = std::max<int64_t>(1, n / (4 * nb::kTile));
+        p.splits = (int)std::max<int64_t>(1, std::min(s, max_s));
+    }
+    return p;
+}
+
+// Normalises a plan for (n, n_i): fills zero fields, rounds split lengths.
+void finish_plan(Plan &p, int64_t n, int32_t n_i, int64_t *split_len)
+{
+    if (p.splits < 1) p.splits = 1;
+    const int64_t unit = p.mapping == 1 ? nb::kTile : nb::kWave;
+    const int64_t units = (n + unit - 1) / unit;
+    int64_t per = (units + p.splits - 1) / p.splits;
+    if (per < 1) per = 1;
+    *split_len = per * unit;
+    p.splits = (int)((n + *split_len - 1) / *split_len);
+    if (p.splits < 1) p.splits = 1;
+    if (p.mapping == 1 && p.splits > 65535) {   // grid.y limit
+        *split_len = ((n + 65534) / 65535 + unit - 1) / unit * unit;
+        p.splits = (int)((n + *split_len - 1) / *split_len);
+    }
+    (void)n_i;
+}
+
+}  // namespace nbrt
+
+using namespace nbrt;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int nb_version(void) { return 10000; }   // 1.0.0
+
+const char *nb_error_string(int code)
+{
+    switch (code) {
+    case NB_OK: return "ok";
+    case NB_ERR_INVALID_ARG: return "invalid argument";
+    case NB_ERR_HIP: return "HIP runtime error";
+    case NB_ERR_OOM: return "out of device memory or over the scratch limit";
+    case NB_ERR_UNSUPPORTED: return "unsupported device or plan";
+    default: return "unknown error";
+    }
+}
+
+int nb_ctx_create(nb_ctx **out, int device, void *hip_stream)
+{
+    if (!out) return NB_ERR_INVALID_ARG;
+    *out = nullptr;
+    nb_ctx *ctx = new (std::nothrow) nb_ctx();
+    if (!ctx) return NB_ERR_OOM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (device >= 0) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+            (void)hipGetLastError();
+            delete ctx;
+            return NB_ERR_UNSUPPORTED;
+        }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+            delete ctx;
+            return NB_ERR_HIP;
+        }
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            delete ctx;
+            return NB_ERR_UNSUPPORTED;
+        }
+        ctx->cu_count = prop.multiProcessorCount;
+        ctx->usable = true;
+    }
+    // device < 0: a host-only context that validates arguments and launches
+    // nothing (every compute call returns NB_ERR_UNSUPPORTED after checks).
+    *out = ctx;
+    return NB_OK;
+}
+
+int nb_ctx_set_stream(nb_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return NB_ERR_INVALID_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return NB_OK;
+}
+
+int nb_ctx_destroy(nb_ctx *ctx)
+{
+    if (!ctx) return NB_ERR_INVALID_ARG;
+    if (ctx->usable) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        nbrt::batched_release(ctx);
+        if (ctx->scratch) (void)hipFree(ctx->scratch);
+        for (auto &p : ctx->pending) {
+            (void)hipEventDestroy(p.start);
+            (void)hipEventDestroy(p.stop);
+        }
+        for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    }
+    delete ctx;
+    return NB_OK;
+}
+
+int nb_ctx_set_plan(nb_ctx *ctx, int mapping, int rows_per_lane, int splits)
+{
+    if (!ctx) return NB_ERR_INVALID_ARG;
+    if (mapping < 0 || mapping > 2 || splits < 0) return NB_ERR_INVALID_ARG;
+    if (!(rows_per_lane == 0 || rows_per_lane == 1 || rows_per_lane == 2 || rows_per_lane == 4))
+        return NB_ERR_INVALID_ARG;
+    ctx->forced = Plan{mapping, rows_per_lane, splits};
+    ctx->has_forced = mapping != 0 || rows_per_lane != 0 || splits != 0;
+    return NB_OK;
+}
+
+int nb_ctx_last_plan(nb_ctx *ctx, char *buf, int len)
+{
+    if (!ctx || !buf || len <= 0) return NB_ERR_INVALID_ARG;
+    std::snprintf(buf, (size_t)len, "%s", ctx->last_plan);
+    return NB_OK;
+}
+
+int nb_ctx_set_scratch_limit(nb_ctx *ctx, int64_t bytes)
+{
+    if (!ctx || bytes < 0) return NB_ERR_INVALID_ARG;
+    ctx->scratch_limit = (size_t)bytes;
+    return NB_OK;
+}
+
+int nb_ctx_enable_timing(nb_ctx *ctx, int on)
+{
+    if (!ctx) return NB_ERR_INVALID_ARG;
+    ctx->timing = on != 0;
+    return NB_OK;
+}
+
+int nb_ctx_kernel_time(nb_ctx *ctx, int kernel_class, double *ms, int64_t *launches)
+{
+    if (!ctx || kernel_class < 0 || kernel_class >= NB_NCLASS || !ms || !launches)
+        return NB_ERR_INVALID_ARG;
+    if (ctx->usable) {
+        for (auto &p : ctx->pending) {
+            hipError_t e = hipEventSynchronize(p.stop);
+            if (e != hipSuccess) return hip_fail(ctx, e);
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, p.start, p.stop);
+            if (e != hipSuccess) return hip_fail(ctx, e);
+            ctx->ms[p.cls] += t;
+            ctx->launches[p.cls] += 1;
+            ctx->free_events.push_back(p.start);
+            ctx->free_events.push_back(p.stop);
+        }
+        ctx->pending.clear();
+    }
+    *ms = ctx->ms[kernel_class];
+    *launches = ctx->launches[kernel_class];
+    return NB_OK;
+}
+
+int nb_ctx_reset_timing(nb_ctx *ctx)
+{
+    if (!ctx) return NB_ERR_INVALID_ARG;
+    double ms;
+    int64_t l;
+    int rc = nb_ctx_kernel_time(ctx, 0, &ms, &l);   // drains pending events
+    if (rc != NB_OK) return rc;
+    for (int k = 0; k < NB_NCLASS; ++k) {
+        ctx->ms[k] = 0.0;
+        ctx->launches[k] = 0;
+    }
+    return NB_OK;
+}
+
+int nb_predict(nb_ctx *ctx, int64_t n, double t, const double *x, const double *v,
+               const double *a, const double *jrk, const double *t0, const double *m,
+               double *xp, double *vp, float *m32)
+{
+    if (!ctx || n <= 0 || n > INT32_MAX) return NB_ERR_INVALID_ARG;
+    if (!x || !v || !a || !jrk || !t0 || !xp || !vp) return NB_ERR_INVALID_ARG;
+    if ((m == nullptr) != (m32 == nullptr)) return NB_ERR_INVALID_ARG;
+    if (!std::isfinite(t)) return NB_ERR_INVALID_ARG;
+    if (!ctx->usable) return NB_ERR_UNSUPPORTED;
+    hipEvent_t ev[2];
+    hipError_t e = timed_begin(ctx, NB_CLASS_PREDICT, ev);
+    if (e == hipSuccess) e = nb::launch_predict(n, t, x, v, a, jrk, t0, m, xp, vp, m32, ctx->stream);
+    if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_PREDICT, ev);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
+}
+
+int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                     const double *m, int32_t n_i, const int32_t *i_block, const double *rs2,
+                     int32_t nb_cap, nb_precision prec, double *acc, double *jerk,
+                     int32_t *nb_count, int32_t *nb_list, int32_t *overflow, uint32_t *status)
+{
+    if (!ctx || n <= 0 || n > INT32_MAX || n_i < 0 || nb_cap < 0) return NB_ERR_INVALID_ARG;
+    if (prec != NB_FP64 && prec != NB_MIXED) return NB_ERR_INVALID_ARG;
+    if (!xp || !vp || !m || !overflow) return NB_ERR_INVALID_ARG;
+    if (n_i > 0 && (!i_block || !rs2 || !acc || !jerk || !nb_count)) return NB_ERR_INVALID_ARG;
+    if (n_i > 0 && nb_cap > 0 && !nb_list) return NB_ERR_INVALID_ARG;
+    if (!ctx->usable) return NB_ERR_UNSUPPORTED;
+
+    hipError_t e = hipMemsetAsync(overflow, 0, sizeof(int32_t), ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    if (n_i == 0) {
+        std::snprintf(ctx->last_plan, sizeof ctx->last_plan, "empty");
+        return NB_OK;
+    }
+    const bool mixed = prec == NB_MIXED;
+    Plan p = auto_plan(ctx, n, n_i, mixed);
+    if (ctx->has_forced) {
+        if (ctx->forced.mapping) p.mapping = ctx->forced.mapping;
+        if (ctx->forced.rows_per_lane) p.rows_per_lane = ctx->forced.rows_per_lane;
+        if (ctx->forced.splits) p.splits = ctx->forced.splits;
+    }
+    int64_t split_len = 0;
+    finish_plan(p, n, n_i, &split_len);
+
+    nb::ForceArgs fa{};
+    fa.n = n;
+    fa.xp = xp;
+    fa.vp = vp;
+    fa.m = m;
+    fa.n_i = n_i;
+    fa.i_block = i_block;
+    fa.rs2 = rs2;
+    fa.cap = nb_cap;
+    fa.acc = acc;
+    fa.jerk = jerk;
+    fa.nb_count = nb_count;
+    fa.nb_list = nb_list;
+    fa.overflow = overflow;
+    fa.status = status;
+    fa.splits = p.splits;
+    fa.split_len = split_len;
+    if (p.splits > 1) {
+        int rc = ensure_scratch(ctx, nb::force_scratch_bytes(p, n_i));
+        if (rc != NB_OK) return rc;
+    }
+    nb::force_bind_scratch(fa, ctx->scratch);
+    std::snprintf(ctx->last_plan, sizeof ctx->last_plan,
+                  "mapping=%d rows_per_lane=%d splits=%d split_len=%lld prec=%s", p.mapping,
+                  p.rows_per_lane, p.splits, (long long)split_len, mixed ? "mixed" : "fp64");
+
+    hipEvent_t ev[2];
+    e = timed_begin(ctx, NB_CLASS_FORCE, ev);
+    if (e == hipSuccess) e = nb::launch_force(p, mixed, fa, ctx->stream);
+    if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_FORCE, ev);
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    if (p.splits > 1) {
+        e = timed_begin(ctx, NB_CLASS_MERGE, ev);
+        if (e == hipSuccess) e = nb::launch_merge(mixed, fa, ctx->stream);
+        if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_MERGE, ev);
+        if (e != hipSuccess) return hip_fail(ctx, e);
+    }
+    return NB_OK;
+}
+
+int nb_regular_force_adjoint(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                             const double *m, int32_t n_i, const int32_t *i_block,
+                             const double *rs2, const double *w_a, const double *w_j,
+                             double *gx, double *gv, double *gm, uint32_t *status)
+{
+    if (!ctx || n <= 0 || n > INT32_MAX || n_i < 0) return NB_ERR_INVALID_ARG;
+    if (!xp || !vp || !m || !gx || !gv || !gm) return NB_ERR_INVALID_ARG;
+    if (n_i > 0 && (!i_block || !rs2 || !w_a || !w_j)) return NB_ERR_INVALID_ARG;
+    if (!ctx->usable) return NB_ERR_UNSUPPORTED;
+    const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
+    const int64_t target = (int64_t)cus * 8;
+    const int64_t row_wgs = std::max<int64_t>(1, (n_i + nb::kBlock - 1) / nb::kBlock);
+    const int64_t body_wgs = (n + nb::kBlock - 1) / nb::kBlock;
+    int row_splits = (int)std::max<int64_t>(
+        1, std::min<int64_t>((target + row_wgs - 1) / row_wgs, std::max<int64_t>(1, n / 1024)));
+    int body_splits = (int)std::max<int64_t>(
+        1, std::min<int64_t>((target + body_wgs - 1) / body_wgs,
+                             std::max<int64_t>(1, (n_i + 127) / 128)));
+    int rc = ensure_scratch(ctx, nb::adjoint_scratch_bytes(n, n_i, row_splits, body_splits));
+    if (rc != NB_OK) return rc;
+    nb::AdjointArgs aa{};
+    aa.n = n;
+    aa.xp = xp;
+    aa.vp = vp;
+    aa.m = m;
+    aa.n_i = n_i;
+    aa.i_block = i_block;
+    aa.rs2 = rs2;
+    aa.w_a = w_a;
+    aa.w_j = w_j;
+    aa.gx = gx;
+    aa.gv = gv;
+    aa.gm = gm;
+    aa.status = status;
+    hipEvent_t ev[2];
+    hipError_t e = timed_begin(ctx, NB_CLASS_ADJOINT, ev);
+    if (e == hipSuccess)
+        e = nb::launch_adjoint_plan(aa, row_splits, body_splits, ctx->scratch, ctx->stream);
+    if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_ADJOINT, ev);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function the
+public header declares, and rejects bad arguments on the host before any GPU
+work (using a host-only context, device -1, which launches nothing)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1504_03687_amd as nb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "nbreg.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nb_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = nb.lib()
+    names = _declared()
+    assert "nb_regular_force" in names and "nb_predict" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert L.nb_version() >= 10000
+    assert nb.lib().nb_error_string(-1) == b"invalid argument"
+
+
+@pytest.fixture
+def host_ctx():
+    L = nb.lib()
+    h = C.c_void_p()
+    assert L.nb_ctx_create(C.byref(h), -1, None) == 0
+    yield h
+    assert L.nb_ctx_destroy(h) == 0
+
+
+def _fake(k):
+    return C.c_void_p(0x1000 * k)   # never dereferenced: host-only context
+
+
+def test_argument_validation(host_ctx):
+    L = nb.lib()
+    p = _fake
+    ok = dict(n=100, n_i=10, cap=8)
+
+    def reg(ctx=host_ctx, n=100, xp=p(1), vp=p(2), m=p(3), n_i=10, ib=p(4), rs2=p(5), cap=8,
+            prec=0, acc=p(6), jerk=p(7), cnt=p(8), lst=p(9), ovf=p(10), st=None):
+        return L.nb_regular_force(ctx, n, xp, vp, m, n_i, ib, rs2, cap, prec, acc, jerk, cnt,
+                                  lst, ovf, st)
+
+    E = -1
+    assert reg(ctx=None) == E
+    assert reg(n=0) == E and reg(n=-5) == E and reg(n=2 ** 31) == E
+    assert reg(n_i=-1) == E and reg(cap=-1) == E and reg(prec=2) == E
+    assert reg(xp=None) == E and reg(m=None) == E and reg(ovf=None) == E
+    assert reg(ib=None) == E and reg(acc=None) == E and reg(cnt=None) == E
+    assert reg(lst=None) == E                   # nb_cap > 0 needs a list
+    assert reg(lst=None, cap=0) == -4           # valid; host-only context cannot launch
+    assert reg(n_i=0, ib=None, rs2=None, acc=None, jerk=None, cnt=None, lst=None) == -4
+    assert reg() == -4 and reg(prec=1) == -4
+    # predictor
+    pr = lambda **k: L.nb_predict(k.get("ctx", host_ctx), k.get("n", 10), k.get("t", 0.5),
+                                  p(1), p(2), p(3), p(4), p(5), k.get("m", None), p(6), p(7),
+                                  k.get("m32", None))
+    assert pr(n=0) == E and pr(m=p(8)) == E and pr(t=float("nan")) == E
+    assert pr() == -4 and pr(m=p(8), m32=p(9)) == -4
+    # plan override
+    assert L.nb_ctx_set_plan(host_ctx, 3, 0, 0) == E
+    assert L.nb_ctx_set_plan(host_ctx, 1, 3, 0) == E
+    assert L.nb_ctx_set_plan(host_ctx, 1, 2, 4) == 0
+    assert L.nb_ctx_set_plan(host_ctx, 0, 0, 0) == 0
+    assert L.nb_ctx_set_scratch_limit(host_ctx, -1) == E
+
+
+def test_gpu_context_refused_without_gfx950():
+    """Without an MI355X the library refuses a device context (no CPU fallback)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert nb.lib().nb_ctx_create(C.byref(h), 0, None) == -4

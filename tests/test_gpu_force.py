@@ -1,0 +1,243 @@
+"""GPU parity of the predictor and the regular-force kernels against the CPU
+oracle, through the C ABI (via the ctypes binding).
+
+Bars: predictor and neighbour lists/counts bit-exact; acc/jerk per-row
+relative error <= 1e-12 (FP64 kernels) and <= 5e-6 (mixed kernels).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1504_03687_amd as nb
+import workloads as W
+from gpu_util import (TOL_FP64, TOL_MIXED, check_lists, compare_force, dev, host, row_rel_err,
+                      say)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": TOL_FP64, "mixed": TOL_MIXED}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = nb.Context(0)
+    yield c
+    c.close()
+
+
+def _predict_dev(ctx, s):
+    xp, vp, m32 = nb.predict(dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(s["t0"]),
+                             s["t"], m=dev(s["m"]), ctx=ctx)
+    return xp, vp, m32
+
+
+@pytest.mark.parametrize("n", [1, 257, 4099])
+def test_predict_bitwise(ctx, n):
+    say(f"predict n={n}")
+    rng = np.random.default_rng(n)
+    x, v, a, jk = (rng.standard_normal((3, n)) for _ in range(4))
+    t0 = -np.ldexp(1.0, -rng.integers(3, 20, n))
+    m = rng.random(n)
+    s = dict(x=x, v=v, a=a, jk=jk, t0=t0, t=0.375, m=m)
+    xp, vp, m32 = _predict_dev(ctx, s)
+    torch.cuda.synchronize()
+    ox, ov = oracle.predict(0.375, x, v, a, jk, t0)
+    assert np.array_equal(host(xp), ox) and np.array_equal(host(vp), ov)
+    assert np.array_equal(host(m32), m.astype(np.float32))
+    # in place
+    xd, vd = dev(x), dev(v)
+    nb.predict(xd, vd, dev(a), dev(jk), dev(t0), 0.375, out=(xd, vd), ctx=ctx)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(xd), ox) and np.array_equal(host(vd), ov)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_config1_all_active(ctx, prec):
+    """N = 1024 equal-mass Plummer, every body active, nb_cap 256."""
+    say(f"config1 {prec}")
+    s = W.config1()
+    xp, vp, _ = _predict_dev(ctx, s)
+    ox, ov = oracle.predict(s["t"], s["x"], s["v"], s["a"], s["jk"], s["t0"])
+    assert np.array_equal(host(xp), ox) and np.array_equal(host(vp), ov)
+    res = nb.regular_force(xp, vp, dev(s["m"]), dev(s["i_block"]), dev(s["rs2"]), s["nb_cap"],
+                           prec, ctx=ctx)
+    ea, ej = compare_force(res, ox, ov, s["m"], s["i_block"], s["rs2"], s["nb_cap"], TOL[prec])
+    say(f"  plan {ctx.last_plan()}  max err acc {ea:.2e} jerk {ej:.2e}")
+
+
+PLANS = [(1, 1, 1), (1, 2, 1), (1, 4, 1), (1, 1, 3), (1, 2, 5), (1, 4, 2),
+         (2, 1, 1), (2, 2, 4), (2, 4, 7), (2, 4, 1), (2, 1, 13)]
+
+
+def _ragged_case(seed=31, n=3001, n_i=777):
+    s = W.small_state(seed, n, k_nn=40)
+    rng = np.random.default_rng(seed)
+    ib = rng.integers(0, n, n_i).astype(np.int32)     # duplicates allowed
+    ib[5] = ib[6]
+    rs2 = s["rs2"][ib].copy()
+    rs2[10] = 0.0
+    rs2[11] = -1.0
+    rs2[12] = s["rs2"].max() * 6                      # many neighbours
+    return s, ib, rs2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("plan", PLANS, ids=lambda p: "m%d-r%d-s%d" % p)
+def test_plans_ragged(ctx, plan, prec):
+    say(f"plan {plan} {prec}")
+    s, ib, rs2 = _ragged_case()
+    ctx.set_plan(*plan)
+    try:
+        for cap in (48, 0):
+            res = nb.regular_force(dev(s["x"]), dev(s["v"]), dev(s["m"]), dev(ib), dev(rs2), cap,
+                                   prec, ctx=ctx)
+            compare_force(res, s["x"], s["v"], s["m"], ib, rs2, cap, TOL[prec])
+    finally:
+        ctx.set_plan(0, 0, 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_segment_rebuild(ctx, prec):
+    """Rows with hundreds of neighbours per j-range overflow the per-split
+    scratch segments; the merge must rebuild them in ascending order."""
+    say(f"segment rebuild {prec}")
+    s = W.small_state(41, 5000, k_nn=32)
+    ib = np.arange(0, 5000, 9, dtype=np.int32)
+    rs2 = np.full(ib.size, np.quantile(s["rs2"], 0.5) * 8)
+    for plan in ((1, 1, 2), (1, 2, 3), (2, 4, 3), (2, 1, 5)):
+        ctx.set_plan(*plan)
+        try:
+            for cap in (150, 2000):
+                res = nb.regular_force(dev(s["x"]), dev(s["v"]), dev(s["m"]), dev(ib), dev(rs2),
+                                       cap, prec, ctx=ctx)
+                compare_force(res, s["x"], s["v"], s["m"], ib, rs2, cap, TOL[prec])
+        finally:
+            ctx.set_plan(0, 0, 0)
+    assert host(res[2]).max() > 200
+
+
+def test_edge_cases(ctx):
+    say("edge cases")
+    s = W.small_state(51, 600)
+    x, v, m = dev(s["x"]), dev(s["v"]), dev(s["m"])
+    # bad indices give zero rows, count 0 and the status bit
+    ib = np.array([3, 600, -1, 599, 3], np.int32)
+    rs2 = s["rs2"][np.clip(ib, 0, 599)]
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    acc, jerk, cnt, lst, ovf = nb.regular_force(x, v, m, dev(ib), dev(rs2), 16, "fp64", status=st,
+                                                ctx=ctx)
+    torch.cuda.synchronize()
+    assert int(st.item()) & nb.STATUS_BAD_INDEX
+    assert not host(acc)[:, 1:3].any() and not host(jerk)[:, 1:3].any()
+    assert host(cnt)[1] == 0 and host(cnt)[2] == 0
+    assert np.array_equal(host(acc)[:, 0], host(acc)[:, 4])
+    # empty block
+    e = nb.regular_force(x, v, m, dev(np.zeros(0, np.int32)), dev(np.zeros(0)), 8, "mixed",
+                         ctx=ctx)
+    assert int(e[4].item()) == 0
+    # a single body: no pairs at all
+    one = nb.regular_force(dev(s["x"][:, :1]), dev(s["v"][:, :1]), dev(s["m"][:1]),
+                           dev(np.zeros(1, np.int32)), dev(np.ones(1)), 4, "fp64", ctx=ctx)
+    assert not host(one[0]).any() and host(one[2])[0] == 0
+    # coincident distinct bodies outside each other's radius: non-finite flag
+    x2 = s["x"][:, :4].copy()
+    x2[:, 1] = x2[:, 0]
+    st.zero_()
+    bad = nb.regular_force(dev(x2), dev(s["v"][:, :4]), dev(s["m"][:4]),
+                           dev(np.array([0], np.int32)), dev(np.zeros(1)), 4, "mixed",
+                           status=st, ctx=ctx)
+    torch.cuda.synchronize()
+    assert int(st.item()) & nb.STATUS_NONFINITE
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_determinism_and_block_independence(ctx, prec):
+    """A fixed plan gives bitwise-identical rows whatever else is in the block,
+    and identical results on a re-run."""
+    say(f"determinism {prec}")
+    s = W.small_state(61, 4096, k_nn=48)
+    x, v, m = dev(s["x"]), dev(s["v"]), dev(s["m"])
+    full = np.arange(4096, dtype=np.int32)
+    for plan in ((1, 1, 4), (2, 2, 8)):
+        ctx.set_plan(*plan)
+        try:
+            a0 = [host(t) for t in nb.regular_force(x, v, m, dev(full), dev(s["rs2"]), 128, prec,
+                                                   ctx=ctx)]
+            a1 = [host(t) for t in nb.regular_force(x, v, m, dev(full), dev(s["rs2"]), 128, prec,
+                                                   ctx=ctx)]
+            for p, q in zip(a0, a1):
+                assert np.array_equal(p, q)
+            for sub in (np.array([1234], np.int32), np.arange(100, 132, dtype=np.int32)):
+                r = [host(t) for t in nb.regular_force(x, v, m, dev(sub), dev(s["rs2"][sub]),
+                                                      128, prec, ctx=ctx)]
+                assert np.array_equal(r[0], a0[0][:, sub]) and np.array_equal(r[1], a0[1][:, sub])
+                assert np.array_equal(r[2], a0[2][sub])
+        finally:
+            ctx.set_plan(0, 0, 0)
+
+
+def test_power_of_two_scaling_fp64(ctx):
+    """x -> 2x, rs2 -> 4 rs2 leaves the lists unchanged and scales acc by 1/4
+    and jerk by 1/8 exactly in the FP64 kernels."""
+    say("scaling")
+    s = W.small_state(71, 2048, k_nn=32)
+    ib = np.arange(2048, dtype=np.int32)
+    base = [host(t) for t in nb.regular_force(dev(s["x"]), dev(s["v"]), dev(s["m"]), dev(ib),
+                                              dev(s["rs2"]), 64, "fp64", ctx=ctx)]
+    sc = [host(t) for t in nb.regular_force(dev(2 * s["x"]), dev(s["v"]), dev(s["m"]), dev(ib),
+                                            dev(4 * s["rs2"]), 64, "fp64", ctx=ctx)]
+    assert np.array_equal(base[2], sc[2]) and np.array_equal(base[3], sc[3])
+    assert np.array_equal(sc[0], base[0] / 4) and np.array_equal(sc[1], base[1] / 8)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_config2_blocks(ctx, prec):
+    """N = 131072 Plummer + Kroupa: random blocks of 1, 32, 1024, 16384 rows
+    in full and the all-active block on 512 sampled rows."""
+    s = W.config2()
+    xp, vp, _ = _predict_dev(ctx, s)
+    ox, ov = oracle.predict(s["t"], s["x"], s["v"], s["a"], s["jk"], s["t0"])
+    assert np.array_equal(host(xp), ox)
+    m = dev(s["m"])
+    for size, blk in s["blocks"].items():
+        say(f"config2 {prec} n_i={size}")
+        rs2 = s["rs2"][blk]
+        res = nb.regular_force(xp, vp, m, dev(blk), dev(rs2), s["nb_cap"], prec, ctx=ctx)
+        rows = None if size <= 16384 else np.random.default_rng(size).choice(size, 512,
+                                                                             replace=False)
+        ea, ej = compare_force(res, ox, ov, s["m"], blk, rs2, s["nb_cap"], TOL[prec], rows=rows)
+        say(f"  plan {ctx.last_plan()}  err acc {ea:.2e} jerk {ej:.2e}")
+
+
+def _config3_sample_rows(s, blk, k=384):
+    """Rows of block blk to check: the most central bodies, binary components
+    and a random remainder."""
+    r = np.sqrt((s["x"] ** 2).sum(0))[blk]
+    central = np.argsort(r)[:64]
+    binaries = np.nonzero(blk < 2 * s["n_bin"])[0][:64]
+    rng = np.random.default_rng(3)
+    rest = rng.choice(blk.size, min(k, blk.size), replace=False)
+    return np.unique(np.concatenate([central, binaries, rest]))[:k + 128]
+
+
+@pytest.mark.parametrize("level", [3, 12])
+def test_config3_million_body(ctx, level):
+    """N = 2^20 Plummer + Kroupa with 5% binaries, both precisions, at the full
+    block (level 3) and a deep block level; sampled rows vs the oracle."""
+    s = W.config3()
+    t, t0, blk = W.config3_level(s, level)
+    say(f"config3 level {level}: n_i={blk.size}")
+    xp, vp, _ = nb.predict(dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(t0), t,
+                           ctx=ctx)
+    ox, ov = oracle.predict(t, s["x"], s["v"], s["a"], s["jk"], t0)
+    assert np.array_equal(host(xp), ox) and np.array_equal(host(vp), ov)
+    rows = _config3_sample_rows(s, blk)
+    m = dev(s["m"])
+    rs2 = s["rs2"][blk]
+    for prec in ("mixed", "fp64"):
+        res = nb.regular_force(xp, vp, m, dev(blk), dev(rs2), s["nb_cap"], prec, ctx=ctx)
+        ea, ej = compare_force(res, ox, ov, s["m"], blk, rs2, s["nb_cap"], TOL[prec], rows=rows)
+        say(f"  {prec} plan {ctx.last_plan()}  err acc {ea:.2e} jerk {ej:.2e}")
+        del res
+        torch.cuda.empty_cache()
