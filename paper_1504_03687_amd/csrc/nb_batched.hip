@@ -1,0 +1,383 @@
+// Batched ensemble of independent clusters in one persistent launch.
+//
+// The paper integrates one cluster at a time; running many uneven clusters
+// (an ensemble of star-cluster models) through one launch is this library's
+// own extension of the regular-force step of section 3.2.1.  Each cluster's
+// rows are cut into row tiles of kBlock rows (one work-group) and, for large
+// clusters, its bodies into j-splits; every (cluster, row tile, split) is one
+// work item.  Items are sorted longest-first on the host; a persistent grid
+// of (CUs x resident work-groups) pulls them from an atomic counter, so short
+// and long clusters share the chip without per-cluster launches.  Clusters
+// with one split write their outputs directly; the others go through split
+// slots and the same merge as the single-block launch.  The launch sequence
+// (counter reset, overflow reset, persistent kernel, merge) is captured once
+// per shape into a HIP graph and replayed.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "../../include/nbreg.h"
+#include "nb_rows.h"
+#include "nb_runtime.h"
+
+namespace nb {
+namespace {
+
+template <bool MIXED, int IR>
+__global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A)
+{
+    __shared__ JBody tile[2][kTile];
+    __shared__ int32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(A.queue, 1);
+        __syncthreads();
+        const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();   // every lane has read s_item before it is replaced
+        if (it >= A.n_items) break;
+        const BItem I = A.items[it];
+        const BCluster C = A.clusters[I.cluster];
+        const int64_t j0 = C.j_begin + (int64_t)I.split * C.split_len;
+        const int64_t j1 = j0 + C.split_len < C.j_end ? j0 + C.split_len : C.j_end;
+        const Dest d{C.splits == 1, C.slot_base + (int64_t)I.split * C.n_rows,
+                     (int64_t)C.row_begin};
+        rows_pass<MIXED, IR>(A.f, tile, I.row0, (int64_t)C.row_begin + C.n_rows, j0, j1, d);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void batched_merge_kernel(BatchArgs A)
+{
+    const int64_t q = (int64_t)blockIdx.x * (kBlock / kWave) +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (q >= A.n_merge_rows) return;
+    const int64_t b = A.merge_rows[q];
+    const BCluster C = A.clusters[A.row_cluster[q]];
+    const MergeGeom g{C.splits, C.slot_base + (b - C.row_begin), (int64_t)C.n_rows, C.j_begin,
+                      C.j_end, C.split_len};
+    merge_row(A.f, b, g);
+}
+
+template <bool MIXED, int IR>
+const void *batched_fn()
+{
+    return (const void *)&batched_kernel<MIXED, IR>;
+}
+
+}  // namespace
+
+int batched_max_blocks_per_cu(bool mixed, int rows_per_lane)
+{
+    const void *fn = mixed ? (rows_per_lane == 2 ? batched_fn<true, 2>() : batched_fn<true, 1>())
+                           : (rows_per_lane == 2 ? batched_fn<false, 2>() : batched_fn<false, 1>());
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlock, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return blocks > 0 ? blocks : 1;
+}
+
+hipError_t launch_batched(bool mixed, int rows_per_lane, int grid, const BatchArgs &a,
+                          hipStream_t s)
+{
+    if (mixed) {
+        if (rows_per_lane == 2)
+            hipLaunchKernelGGL((batched_kernel<true, 2>), dim3(grid), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((batched_kernel<true, 1>), dim3(grid), dim3(kBlock), 0, s, a);
+    } else {
+        if (rows_per_lane == 2)
+            hipLaunchKernelGGL((batched_kernel<false, 2>), dim3(grid), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((batched_kernel<false, 1>), dim3(grid), dim3(kBlock), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_merge(const BatchArgs &a, hipStream_t s)
+{
+    if (a.n_merge_rows <= 0) return hipSuccess;
+    const int per = kBlock / kWave;
+    hipLaunchKernelGGL(batched_merge_kernel, dim3((unsigned)((a.n_merge_rows + per - 1) / per)),
+                       dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace nb
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace nbrt {
+
+struct BatchedCache {
+    // key
+    std::vector<int64_t> j_off, i_off;
+    int32_t cap = 0;
+    int prec = 0;
+    int rows_per_lane = 1;
+    int forced_splits = 0;
+    const void *ptrs[11] = {};
+    // device state
+    void *dmem = nullptr;
+    nb::BatchArgs args{};
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
+static uint64_t g_use_clock = 0;
+
+static void release_one(BatchedCache *c)
+{
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->dmem) (void)hipFree(c->dmem);
+    delete c;
+}
+
+void batched_release(nb_ctx *ctx)
+{
+    for (auto *c : ctx->batched) release_one(c);
+    ctx->batched.clear();
+}
+
+static size_t r256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Builds the work list, uploads metadata, and captures the launch graph.
+static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, bool mixed)
+{
+    const int32_t C = (int32_t)c->j_off.size() - 1;
+    std::vector<nb::BCluster> cl((size_t)C);
+    int64_t slots = 0;
+    for (int32_t k = 0; k < C; ++k) {
+        const int64_t nc = c->j_off[k + 1] - c->j_off[k];
+        const int64_t rc = c->i_off[k + 1] - c->i_off[k];
+        int64_t S;
+        if (nc <= 0) {
+            S = 1;
+        } else if (c->forced_splits > 0) {
+            S = std::min<int64_t>(c->forced_splits, (nc + nb::kTile - 1) / nb::kTile);
+        } else {
+            S = (nc + 65535) / 65536;   // bounds the largest item's work
+        }
+        const int64_t tiles = std::max<int64_t>(1, (nc + nb::kTile - 1) / nb::kTile);
+        const int64_t per = (tiles + S - 1) / S;
+        const int64_t split_len = per * nb::kTile;
+        S = nc > 0 ? (nc + split_len - 1) / split_len : 1;
+        nb::BCluster &b = cl[(size_t)k];
+        b.j_begin = c->j_off[k];
+        b.j_end = c->j_off[k + 1];
+        b.split_len = split_len;
+        b.row_begin = (int32_t)c->i_off[k];
+        b.n_rows = (int32_t)rc;
+        b.splits = (int32_t)S;
+        b.pad = 0;
+        b.slot_base = 0;
+        if (S > 1) {
+            b.slot_base = slots;
+            slots += S * rc;
+        }
+    }
+    // work items, longest first
+    struct W {
+        int64_t work;
+        nb::BItem it;
+    };
+    std::vector<W> items;
+    const int64_t rows_per_item = (int64_t)c->rows_per_lane * nb::kBlock;
+    std::vector<int32_t> merge_rows, row_cluster;
+    for (int32_t k = 0; k < C; ++k) {
+        const nb::BCluster &b = cl[(size_t)k];
+        for (int64_t r = 0; r < b.n_rows; r += rows_per_item) {
+            const int64_t nr = std::min<int64_t>(rows_per_item, b.n_rows - r);
+            for (int32_t s = 0; s < b.splits; ++s) {
+                const int64_t j0 = b.j_begin + s * b.split_len;
+                const int64_t j1 = std::min<int64_t>(b.j_end, j0 + b.split_len);
+                items.push_back({nr * std::max<int64_t>(j1 - j0, 1),
+                                 nb::BItem{k, (int32_t)(b.row_begin + r), s, 0}});
+            }
+        }
+        if (b.splits > 1)
+            for (int32_t r = 0; r < b.n_rows; ++r) {
+                merge_rows.push_back(b.row_begin + r);
+                row_cluster.push_back(k);
+            }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const W &x, const W &y) { return x.work > y.work; });
+    std::vector<nb::BItem> it_dev(items.size());
+    for (size_t q = 0; q < items.size(); ++q) it_dev[q] = items[q].it;
+
+    // one device allocation: queue | clusters | items | merge rows | row cluster | slots
+    const size_t b_queue = 256;
+    const size_t b_cl = r256(cl.size() * sizeof(nb::BCluster));
+    const size_t b_it = r256(std::max<size_t>(1, it_dev.size()) * sizeof(nb::BItem));
+    const size_t b_mr = r256(std::max<size_t>(1, merge_rows.size()) * sizeof(int32_t));
+    const size_t b_slots = nb::slot_scratch_bytes(slots);
+    const size_t total = b_queue + b_cl + 2 * b_mr + b_it + b_slots;
+    if (ctx->scratch_limit && total > ctx->scratch_limit) return NB_ERR_OOM;
+    hipError_t e = hipMalloc(&c->dmem, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->dmem = nullptr;
+        return NB_ERR_OOM;
+    }
+    char *p = (char *)c->dmem;
+    int32_t *queue = (int32_t *)p;
+    p += b_queue;
+    nb::BCluster *dcl = (nb::BCluster *)p;
+    p += b_cl;
+    nb::BItem *dit = (nb::BItem *)p;
+    p += b_it;
+    int32_t *dmr = (int32_t *)p;
+    p += b_mr;
+    int32_t *drc = (int32_t *)p;
+    p += b_mr;
+    void *dslots = p;
+
+    e = hipMemcpy(dcl, cl.data(), cl.size() * sizeof(nb::BCluster), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !it_dev.empty())
+        e = hipMemcpy(dit, it_dev.data(), it_dev.size() * sizeof(nb::BItem),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !merge_rows.empty()) {
+        e = hipMemcpy(dmr, merge_rows.data(), merge_rows.size() * sizeof(int32_t),
+                      hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(drc, row_cluster.data(), row_cluster.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e);
+
+    nb::BatchArgs &A = c->args;
+    A.f = f;
+    nb::bind_slot_scratch(A.f, slots, dslots);
+    A.f.splits = 0;          // per-cluster
+    A.f.split_len = 0;
+    A.clusters = dcl;
+    A.items = dit;
+    A.n_items = (int32_t)it_dev.size();
+    A.queue = queue;
+    A.merge_rows = dmr;
+    A.row_cluster = drc;
+    A.n_merge_rows = (int32_t)merge_rows.size();
+    const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
+    c->grid = cus * nb::batched_max_blocks_per_cu(mixed, c->rows_per_lane);
+    if (A.n_items < c->grid) c->grid = std::max(1, A.n_items);
+
+    // capture the launch sequence on a private stream (default priority)
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = nb::launch_fill_i32(queue, 0, 1, cs);
+        if (le == hipSuccess) le = nb::launch_fill_i32(f.overflow, 0, 1, cs);
+        if (le == hipSuccess) le = nb::launch_batched(mixed, c->rows_per_lane, c->grid, A, cs);
+        if (le == hipSuccess) le = nb::launch_batched_merge(A, cs);
+        e = hipStreamEndCapture(cs, &c->graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    return NB_OK;
+}
+
+}  // namespace nbrt
+
+using namespace nbrt;
+
+extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const int64_t *j_off_host,
+                                        const int64_t *i_off_host, const double *xp,
+                                        const double *vp, const double *m,
+                                        const int32_t *i_block, const double *rs2,
+                                        int32_t nb_cap, nb_precision prec, double *acc,
+                                        double *jerk, int32_t *nb_count, int32_t *nb_list,
+                                        int32_t *overflow, uint32_t *status)
+{
+    if (!ctx || n_clusters < 1 || !j_off_host || !i_off_host || nb_cap < 0)
+        return NB_ERR_INVALID_ARG;
+    if (prec != NB_FP64 && prec != NB_MIXED) return NB_ERR_INVALID_ARG;
+    if (j_off_host[0] != 0 || i_off_host[0] != 0) return NB_ERR_INVALID_ARG;
+    for (int32_t k = 0; k < n_clusters; ++k)
+        if (j_off_host[k + 1] < j_off_host[k] || i_off_host[k + 1] < i_off_host[k])
+            return NB_ERR_INVALID_ARG;
+    const int64_t n = j_off_host[n_clusters];
+    const int64_t n_rows = i_off_host[n_clusters];
+    if (n <= 0 || n > INT32_MAX || n_rows > INT32_MAX) return NB_ERR_INVALID_ARG;
+    if (!xp || !vp || !m || !overflow) return NB_ERR_INVALID_ARG;
+    if (n_rows > 0 && (!i_block || !rs2 || !acc || !jerk || !nb_count)) return NB_ERR_INVALID_ARG;
+    if (n_rows > 0 && nb_cap > 0 && !nb_list) return NB_ERR_INVALID_ARG;
+    if (!ctx->usable) return NB_ERR_UNSUPPORTED;
+
+    const bool mixed = prec == NB_MIXED;
+    const int rpl = (ctx->has_forced && ctx->forced.rows_per_lane == 2) ? 2 : 1;
+    const int fsplits = ctx->has_forced ? ctx->forced.splits : 0;
+    const void *ptrs[11] = {xp, vp, m, i_block, rs2, acc, jerk, nb_count, nb_list, overflow,
+                            status};
+    BatchedCache *hit = nullptr;
+    for (auto *c : ctx->batched) {
+        if (c->cap == nb_cap && c->prec == (int)prec && c->rows_per_lane == rpl &&
+            c->forced_splits == fsplits && (int32_t)c->j_off.size() == n_clusters + 1 &&
+            std::memcmp(c->ptrs, ptrs, sizeof ptrs) == 0 &&
+            std::equal(c->j_off.begin(), c->j_off.end(), j_off_host) &&
+            std::equal(c->i_off.begin(), c->i_off.end(), i_off_host)) {
+            hit = c;
+            break;
+        }
+    }
+    if (!hit) {
+        if (ctx->batched.size() >= 4) {   // evict the least recently used shape
+            auto old = std::min_element(ctx->batched.begin(), ctx->batched.end(),
+                                        [](const BatchedCache *x, const BatchedCache *y) {
+                                            return x->last_use < y->last_use;
+                                        });
+            hipError_t e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e);
+            release_one(*old);
+            ctx->batched.erase(old);
+        }
+        auto *c = new BatchedCache();
+        c->j_off.assign(j_off_host, j_off_host + n_clusters + 1);
+        c->i_off.assign(i_off_host, i_off_host + n_clusters + 1);
+        c->cap = nb_cap;
+        c->prec = (int)prec;
+        c->rows_per_lane = rpl;
+        c->forced_splits = fsplits;
+        std::memcpy(c->ptrs, ptrs, sizeof ptrs);
+        nb::ForceArgs f{};
+        f.n = n;
+        f.xp = xp;
+        f.vp = vp;
+        f.m = m;
+        f.n_i = (int32_t)n_rows;
+        f.i_block = i_block;
+        f.rs2 = rs2;
+        f.cap = nb_cap;
+        f.acc = acc;
+        f.jerk = jerk;
+        f.nb_count = nb_count;
+        f.nb_list = nb_list;
+        f.overflow = overflow;
+        f.status = status;
+        int rc = build_cache(ctx, c, f, mixed);
+        if (rc != NB_OK) {
+            release_one(c);
+            return rc;
+        }
+        ctx->batched.push_back(c);
+        hit = c;
+    }
+    hit->last_use = ++g_use_clock;
+    std::snprintf(ctx->last_plan, sizeof ctx->last_plan,
+                  "batched clusters=%d items=%d grid=%d rows_per_lane=%d merge_rows=%d prec=%s",
+                  n_clusters, hit->args.n_items, hit->grid, hit->rows_per_lane,
+                  hit->args.n_merge_rows, mixed ? "mixed" : "fp64");
+    hipEvent_t ev[2];
+    hipError_t e = timed_begin(ctx, NB_CLASS_BATCHED, ev);
+    if (e == hipSuccess) e = hipGraphLaunch(hit->exec, ctx->stream);
+    if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_BATCHED, ev);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
+}

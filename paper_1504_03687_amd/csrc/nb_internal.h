@@ -46,8 +46,9 @@ struct ForceArgs {
     // split layout: split s covers j in [s * split_len, min(n, (s+1) * split_len))
     int32_t splits;
     int64_t split_len;
-    // scratch (splits > 1): part [splits][6][n_i], seg_cnt [splits][n_i],
-    // seg_list [splits][n_i][kSegCap]
+    // scratch (splits > 1): one slot per (row, split), slot = split * n_i + b;
+    // part [6][total_slots], seg_cnt [total_slots], seg_list [total_slots][kSegCap]
+    int64_t total_slots;
     double *part;
     int32_t *seg_cnt;
     int32_t *seg_list;
@@ -61,6 +62,9 @@ struct Plan {
 
 // Scratch bytes needed for a plan (0 when splits == 1).
 size_t force_scratch_bytes(const Plan &p, int32_t n_i);
+// Scratch bytes for 'slots' split slots, and binding of the slot arrays.
+size_t slot_scratch_bytes(int64_t slots);
+void bind_slot_scratch(ForceArgs &a, int64_t slots, void *base);
 // Carves the scratch pointers of 'a' out of 'base'.
 void force_bind_scratch(ForceArgs &a, void *base);
 
@@ -89,38 +93,35 @@ size_t adjoint_scratch_bytes(int64_t n, int32_t n_i, int row_splits, int body_sp
 hipError_t launch_adjoint_plan(const AdjointArgs &a, int row_splits, int body_splits,
                                void *scratch, hipStream_t s);
 
-// Batched ensemble.
-struct BatchItem {
-    int32_t row_begin, row_end;   // rows [row_begin, row_end)
-    int64_t j_begin, j_end;       // j-range of this item (inside its cluster)
-    int32_t slot;                 // split index of this item within its rows
-    int32_t n_slots;              // total splits of this item's rows
+// Batched ensemble: clusters of the concatenated arrays.
+struct BCluster {
+    int64_t j_begin, j_end;   // bodies of the cluster
+    int64_t split_len;        // j per split
+    int64_t slot_base;        // first slot of the cluster (splits > 1 only)
+    int32_t row_begin;        // rows of the cluster
+    int32_t n_rows;
+    int32_t splits;
+    int32_t pad;
+};
+struct BItem {
+    int32_t cluster;
+    int32_t row0;             // first row of the item's row tile
+    int32_t split;
+    int32_t pad;
 };
 struct BatchArgs {
-    int64_t n;
-    const double *xp, *vp, *m;
-    int32_t n_rows;
-    const int32_t *i_block;
-    const double *rs2;
-    int32_t cap;
-    double *acc, *jerk;
-    int32_t *nb_count, *nb_list, *overflow;
-    uint32_t *status;
-    const BatchItem *items;   // device array
+    ForceArgs f;              // n, arrays, outputs, total_slots/part/seg_*
+    const BCluster *clusters;
+    const BItem *items;
     int32_t n_items;
-    int32_t *queue;           // device counter (zeroed before launch)
-    // per-row split bookkeeping: row r's slot s partial lives at
-    // part[(row_slot_base[r] + s) * 6 + k]
-    const int32_t *row_nslots;     // [n_rows]
-    const int64_t *row_slot_base;  // [n_rows]
-    const int64_t *row_j_begin;    // [n_rows] cluster j-range of the row
-    const int64_t *row_j_end;
-    const int64_t *row_split_len;  // [n_rows]
-    double *part;                  // [total_slots][6]
-    int32_t *seg_cnt;              // [total_slots]
-    int32_t *seg_list;             // [total_slots][kSegCap]
+    int32_t *queue;           // work counter, zeroed before each launch
+    const int32_t *merge_rows;   // rows of clusters with splits > 1
+    const int32_t *row_cluster;  // cluster of each merge row
+    int32_t n_merge_rows;
 };
-hipError_t launch_batched(bool mixed, int grid, const BatchArgs &a, hipStream_t s);
-hipError_t launch_batched_merge(bool mixed, const BatchArgs &a, hipStream_t s);
+hipError_t launch_batched(bool mixed, int rows_per_lane, int grid, const BatchArgs &a,
+                          hipStream_t s);
+hipError_t launch_batched_merge(const BatchArgs &a, hipStream_t s);
+int batched_max_blocks_per_cu(bool mixed, int rows_per_lane);
 
 }  // namespace nb

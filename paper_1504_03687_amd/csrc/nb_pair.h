@@ -108,6 +108,32 @@ __device__ __forceinline__ void accum_mixed(Sums<true> &S, float fx, float fy, f
     S.pjz = __builtin_fmaf(q, fz, __builtin_fmaf(mr3, gz, S.pjz));
 }
 
+// FP64 regular term added straight into FP64 running sums (used by the mixed
+// kernels for near pairs, where FP32 rounding would dominate the error).
+__device__ __forceinline__ void add_term_f64(double &ax, double &ay, double &az, double &jx,
+                                             double &jy, double &jz, double dx, double dy,
+                                             double dz, double ux, double uy, double uz,
+                                             double mj)
+{
+    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+    const double y = rsqrt_f64(r2);
+    const double y2 = y * y;
+    const double mr3 = (mj * y) * y2;
+    const double s = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
+    const double q = (s * y2) * (-3.0 * mr3);
+    ax = __builtin_fma(mr3, dx, ax);
+    ay = __builtin_fma(mr3, dy, ay);
+    az = __builtin_fma(mr3, dz, az);
+    jx = __builtin_fma(q, dx, __builtin_fma(mr3, ux, jx));
+    jy = __builtin_fma(q, dy, __builtin_fma(mr3, uy, jy));
+    jz = __builtin_fma(q, dz, __builtin_fma(mr3, uz, jz));
+}
+
+// Mixed kernels evaluate pairs closer than sqrt(kNearFactor) neighbour radii
+// in FP64.  Those few pairs carry the largest terms, so their FP32 rounding
+// would dominate the error of a row whose sum cancels.
+constexpr float kNearFactor = 4.0f;
+
 // Candidate bound for the FP64 plans: every canonical neighbour (and the self
 // pair, r2 = 0) has FP64 r2 < hi, so the exact canonical test only runs for
 // the rare pairs below hi.  The FP32 roundings in r2f change r2 by less than
@@ -118,11 +144,13 @@ __device__ __forceinline__ double cand_bound_f64(float rs2f)
     return h > 1e-300 ? h : 1e-300;
 }
 
-// Candidate bound for the mixed plans, on r2f itself: the neighbour bound, or
-// the smallest normal float when rs2 <= 0 so that the self pair still enters.
+// Candidate bound for the mixed plans, on r2f itself: the near-field bound
+// (neighbours included), or the smallest normal float when rs2 <= 0 so that
+// the self pair still enters.
 __device__ __forceinline__ float cand_bound_f32(float rs2f)
 {
-    return rs2f > 1.17549435e-38f ? rs2f : 1.17549435e-38f;
+    const float h = rs2f * kNearFactor;
+    return h > 1.17549435e-38f ? h : 1.17549435e-38f;
 }
 
 // Keeps the compiler from hoisting the rare exact-test path above its branch

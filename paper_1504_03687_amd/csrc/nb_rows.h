@@ -1,0 +1,368 @@
+// Device building blocks of the regular-force kernels (gfx950): the
+// row-per-lane tile pass and the per-row merge of split partials.  Shared by
+// the single-block launch (nb_force.hip) and the batched ensemble
+// (nb_batched.hip).
+//
+// Slot layout of split partials (both launch kinds): a (row, split) pair owns
+// one slot; part[k * total_slots + slot] holds component k of its FP64 sums
+// (acc x,y,z, jerk x,y,z), seg_cnt[slot] its neighbour count and
+// seg_list[slot * kSegCap ...] the first kSegCap neighbours in ascending j.
+#pragma once
+
+#include "nb_internal.h"
+#include "nb_pair.h"
+
+namespace nb {
+
+struct alignas(16) JBody {
+    double x, y, z, m;
+    double vx, vy, vz;
+    float m32;
+    int32_t pad;
+};
+
+template <bool MIXED>
+struct Row {
+    double x, y, z, vx, vy, vz;
+    double hi;      // FP64 candidate bound (FP64 plan)
+    float rs2f;     // canonical radius
+    float candf;    // FP32 candidate bound (mixed plan)
+    int32_t i;      // body index, -1 when the lane has no row
+    int32_t cnt;    // neighbours found so far (true count)
+    int32_t *lst;   // where this row's neighbours go
+    int32_t lcap;   // capacity of lst
+    Sums<MIXED> S;
+};
+
+// Where the rows of one pass write: straight to the caller's outputs, or to
+// the slots of one split (slot of row b = slot_base + b - row_origin).
+struct Dest {
+    bool direct;
+    int64_t slot_base;
+    int64_t row_origin;
+};
+
+__device__ __forceinline__ int64_t dest_slot(const Dest &d, int64_t b)
+{
+    return d.slot_base + (b - d.row_origin);
+}
+
+template <bool MIXED>
+__device__ __forceinline__ void row_init(Row<MIXED> &R, const ForceArgs &a, int64_t b,
+                                         int64_t row_end, const Dest &d)
+{
+    R.S.zero();
+    R.cnt = 0;
+    R.i = -1;
+    R.x = R.y = R.z = kFar * 0.5;   // inert placeholder
+    R.vx = R.vy = R.vz = 0.0;
+    R.rs2f = -1.0f;
+    R.hi = -1.0;
+    R.candf = -1.0f;
+    R.lst = nullptr;
+    R.lcap = 0;
+    if (b >= row_end) return;
+    const int64_t i = a.i_block[b];
+    if (i < 0 || i >= a.n) return;   // bad index: handled in the epilogue / merge
+    R.i = (int32_t)i;
+    R.x = a.xp[i];
+    R.y = a.xp[a.n + i];
+    R.z = a.xp[2 * a.n + i];
+    R.vx = a.vp[i];
+    R.vy = a.vp[a.n + i];
+    R.vz = a.vp[2 * a.n + i];
+    R.rs2f = (float)a.rs2[b];
+    R.hi = cand_bound_f64(R.rs2f);
+    R.candf = cand_bound_f32(R.rs2f);
+    if (d.direct) {
+        R.lst = a.nb_list + b * (int64_t)a.cap;
+        R.lcap = a.cap;
+    } else {
+        R.lst = a.seg_list + dest_slot(d, b) * kSegCap;
+        R.lcap = kSegCap;
+    }
+}
+
+// One (row, body) pair in the row-per-lane mapping: lane-private append.
+template <bool MIXED>
+__device__ __forceinline__ void pair_rows(Row<MIXED> &R, const JBody &J, int32_t jidx)
+{
+    const double dx = J.x - R.x, dy = J.y - R.y, dz = J.z - R.z;
+    if constexpr (MIXED) {
+        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+        const float r2f = __builtin_fmaf(fz, fz, __builtin_fmaf(fy, fy, fx * fx));
+        bool excl = false;
+        if (r2f < R.candf) {   // neighbour, self, or near pair (FP64 term)
+            double ex = dx, ey = dy, ez = dz;
+            int32_t jj = jidx;
+            opaque(ex, ey, ez);
+            opaque(jj);
+            const bool self = jj == R.i;
+            const bool nbr = (r2f < R.rs2f) && !self;
+            if (nbr) {
+                if (R.cnt < R.lcap) R.lst[R.cnt] = jidx;
+                ++R.cnt;
+            } else if (!self) {
+                add_term_f64(R.S.ax, R.S.ay, R.S.az, R.S.jx, R.S.jy, R.S.jz, ex, ey, ez,
+                             J.vx - R.vx, J.vy - R.vy, J.vz - R.vz, J.m);
+            }
+            excl = true;
+        }
+        accum_mixed(R.S, fx, fy, fz, r2f, J.vx - R.vx, J.vy - R.vy, J.vz - R.vz, J.m32, excl);
+    } else {
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        bool excl = false;
+        if (r2 < R.hi) {
+            double ex = dx, ey = dy, ez = dz;
+            int32_t jj = jidx;
+            opaque(ex, ey, ez);
+            opaque(jj);
+            const bool self = jj == R.i;
+            const bool nbr = (canon_r2f(ex, ey, ez) < R.rs2f) && !self;
+            if (nbr) {
+                if (R.cnt < R.lcap) R.lst[R.cnt] = jidx;
+                ++R.cnt;
+            }
+            excl = nbr || self;
+        }
+        accum_f64(R.S, dx, dy, dz, r2, J.vx - R.vx, J.vy - R.vy, J.vz - R.vz, J.m, excl);
+    }
+}
+
+__device__ __forceinline__ void load_body(JBody &J, const ForceArgs &a, int64_t j, int64_t j1)
+{
+    if (j < j1) {
+        J.x = a.xp[j];
+        J.y = a.xp[a.n + j];
+        J.z = a.xp[2 * a.n + j];
+        J.vx = a.vp[j];
+        J.vy = a.vp[a.n + j];
+        J.vz = a.vp[2 * a.n + j];
+        J.m = a.m[j];
+    } else {
+        J.x = J.y = J.z = kFar;
+        J.vx = J.vy = J.vz = 0.0;
+        J.m = 0.0;
+    }
+    J.m32 = (float)J.m;
+    J.pad = 0;
+}
+
+// One row's final sums and count: to the outputs, or to its split slot.
+template <bool MIXED>
+__device__ __forceinline__ void row_store(const ForceArgs &a, int64_t b, const Dest &d,
+                                          bool valid, const Sums<MIXED> &S, int32_t cnt,
+                                          bool &ovf, bool &bad, bool &nonfin)
+{
+    if (d.direct) {
+        if (!valid) {
+            a.acc[b] = a.acc[a.n_i + b] = a.acc[2 * (int64_t)a.n_i + b] = 0.0;
+            a.jerk[b] = a.jerk[a.n_i + b] = a.jerk[2 * (int64_t)a.n_i + b] = 0.0;
+            a.nb_count[b] = 0;
+            bad = true;
+            return;
+        }
+        a.acc[b] = S.ax;
+        a.acc[a.n_i + b] = S.ay;
+        a.acc[2 * (int64_t)a.n_i + b] = S.az;
+        a.jerk[b] = S.jx;
+        a.jerk[a.n_i + b] = S.jy;
+        a.jerk[2 * (int64_t)a.n_i + b] = S.jz;
+        a.nb_count[b] = cnt;
+        ovf = cnt > a.cap;
+        nonfin = !finite6(S.ax, S.ay, S.az, S.jx, S.jy, S.jz);
+    } else {
+        const int64_t slot = dest_slot(d, b);
+        double *p = a.part + slot;
+        const int64_t T = a.total_slots;
+        p[0] = S.ax;
+        p[T] = S.ay;
+        p[2 * T] = S.az;
+        p[3 * T] = S.jx;
+        p[4 * T] = S.jy;
+        p[5 * T] = S.jz;
+        a.seg_cnt[slot] = cnt;
+    }
+}
+
+__device__ __forceinline__ void flush_flags(const ForceArgs &a, bool ovf, bool bad, bool nonfin)
+{
+    // called in uniform control flow by every lane of the wave
+    const uint64_t o = __ballot(ovf), b = __ballot(bad), f = __ballot(nonfin);
+    if ((threadIdx.x & (kWave - 1)) == 0 && (o | b | f)) {
+        const uint32_t st =
+            (o ? kStOverflow : 0u) | (b ? kStBadIndex : 0u) | (f ? kStNonFinite : 0u);
+        if (o) atomicOr(a.overflow, 1);
+        if (a.status) atomicOr(a.status, st);
+    }
+}
+
+// Rows [row0 + r*kBlock + tid] (r < IR, < row_end) of one work-group against
+// bodies [j0, j1), staged through the double-buffered LDS tile.  Must be
+// called by the whole work-group (it contains barriers).
+template <bool MIXED, int IR>
+__device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTile],
+                                          int64_t row0, int64_t row_end, int64_t j0,
+                                          int64_t j1, const Dest &d)
+{
+    const int tid = threadIdx.x;
+    Row<MIXED> R[IR];
+#pragma unroll
+    for (int r = 0; r < IR; ++r) row_init(R[r], a, row0 + r * kBlock + tid, row_end, d);
+
+    const int64_t ntiles = j1 > j0 ? (j1 - j0 + kTile - 1) / kTile : 0;
+    JBody nxt;
+    if (ntiles > 0) {
+        load_body(nxt, a, j0 + tid, j1);
+        tile[0][tid] = nxt;
+    }
+    __syncthreads();
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int cur = (int)(t & 1);
+        const int64_t tbase = j0 + t * kTile;
+        if (t + 1 < ntiles) load_body(nxt, a, tbase + kTile + tid, j1);
+        const JBody *buf = tile[cur];
+        for (int jj = 0; jj < kTile; jj += kFold) {
+#pragma unroll 4
+            for (int q = 0; q < kFold; ++q) {
+                const JBody &J = buf[jj + q];
+                const int32_t jidx = (int32_t)(tbase + jj + q);
+#pragma unroll
+                for (int r = 0; r < IR; ++r) pair_rows<MIXED>(R[r], J, jidx);
+            }
+            if constexpr (MIXED) {
+#pragma unroll
+                for (int r = 0; r < IR; ++r) R[r].S.fold();
+            }
+        }
+        if (t + 1 < ntiles) tile[cur ^ 1][tid] = nxt;
+        __syncthreads();
+    }
+
+    bool ovf = false, bad = false, nonfin = false;
+#pragma unroll
+    for (int r = 0; r < IR; ++r) {
+        const int64_t b = row0 + r * kBlock + tid;
+        if (b < row_end) {
+            bool o = false, bd = false, f = false;
+            row_store<MIXED>(a, b, d, R[r].i >= 0, R[r].S, R[r].cnt, o, bd, f);
+            ovf |= o;
+            bad |= bd;
+            nonfin |= f;
+        }
+    }
+    flush_flags(a, ovf, bad, nonfin);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Geometry of one row's splits for the merge.
+struct MergeGeom {
+    int32_t splits;
+    int64_t slot0;        // slot of split 0
+    int64_t slot_step;    // slot(s) = slot0 + s * slot_step
+    int64_t j_begin, j_end, split_len;
+};
+
+// Merge of one row by one whole wave: sums the split partials in a fixed
+// order, concatenates neighbour segments in split order (ascending j), writes
+// the true count, and rebuilds any segment that overflowed its scratch
+// capacity by re-running the canonical test over that split's j-range.
+__device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const MergeGeom &g)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t i = a.i_block[b];
+    const bool bad = i < 0 || i >= a.n;
+    const int32_t S = g.splits;
+    const int64_t T = a.total_slots;
+
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int32_t s = lane; s < S; s += kWave) {
+        const double *p = a.part + g.slot0 + (int64_t)s * g.slot_step;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[k] += p[(int64_t)k * T];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+
+    bool ovf = false, nonfin = false;
+    if (bad) {
+        if (lane == 0) {
+            for (int k = 0; k < 3; ++k) {
+                a.acc[(int64_t)k * a.n_i + b] = 0.0;
+                a.jerk[(int64_t)k * a.n_i + b] = 0.0;
+            }
+            a.nb_count[b] = 0;
+        }
+    } else {
+        const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
+        const float rs2f = (float)a.rs2[b];
+        int64_t off = 0;   // uniform: neighbours placed so far (true count)
+        for (int32_t s0 = 0; s0 < S; s0 += kWave) {
+            const int32_t s = s0 + lane;
+            const int64_t slot = g.slot0 + (int64_t)s * g.slot_step;
+            const int32_t c = s < S ? a.seg_cnt[slot] : 0;
+            int64_t inc = c;   // inclusive scan of c over lanes
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int64_t t = __shfl_up(inc, o, kWave);
+                if (lane >= o) inc += t;
+            }
+            const int64_t start = off + inc - c;
+            const bool room = c > 0 && start < a.cap;
+            const bool rebuild = room && c > kSegCap;
+            if (room && !rebuild) {
+                const int64_t take = (int64_t)c < a.cap - start ? c : a.cap - start;
+                const int32_t *src = a.seg_list + slot * kSegCap;
+                int32_t *dst = a.nb_list + b * (int64_t)a.cap + start;
+                for (int64_t q = 0; q < take; ++q) dst[q] = src[q];
+            }
+            uint64_t rb = __ballot(rebuild);
+            while (rb) {   // overflowed segments: the wave rescans them one by one
+                const int q = __builtin_ctzll(rb);
+                rb &= rb - 1;
+                const int32_t sq = __shfl(s, q, kWave);
+                const int64_t st = __shfl(start, q, kWave);
+                const int64_t lim = a.cap - st;
+                const int64_t jb = g.j_begin + (int64_t)sq * g.split_len;
+                const int64_t je = jb + g.split_len < g.j_end ? jb + g.split_len : g.j_end;
+                int64_t placed = 0;
+                for (int64_t base = jb; base < je && placed < lim; base += kWave) {
+                    const int64_t j = base + lane;
+                    bool nbr = false;
+                    if (j < je && j != i) {
+                        const double dx = a.xp[j] - xi, dy = a.xp[a.n + j] - yi,
+                                     dz = a.xp[2 * a.n + j] - zi;
+                        nbr = canon_r2f(dx, dy, dz) < rs2f;
+                    }
+                    const uint64_t nm = __ballot(nbr);
+                    if (nbr) {
+                        const int64_t p = placed + lanes_below(nm);
+                        if (p < lim) a.nb_list[b * (int64_t)a.cap + st + p] = (int32_t)j;
+                    }
+                    placed += __popcll(nm);
+                }
+            }
+            off += __shfl(inc, kWave - 1, kWave);
+        }
+        if (lane == 0) {
+            a.acc[b] = v[0];
+            a.acc[a.n_i + b] = v[1];
+            a.acc[2 * (int64_t)a.n_i + b] = v[2];
+            a.jerk[b] = v[3];
+            a.jerk[a.n_i + b] = v[4];
+            a.jerk[2 * (int64_t)a.n_i + b] = v[5];
+            a.nb_count[b] = (int32_t)off;
+            ovf = off > a.cap;
+            nonfin = !finite6(v[0], v[1], v[2], v[3], v[4], v[5]);
+        }
+    }
+    flush_flags(a, ovf, bad && lane == 0, nonfin);
+}
+
+}  // namespace nb

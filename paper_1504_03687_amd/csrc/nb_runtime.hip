@@ -110,7 +110,7 @@ Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed)
         p.splits = (int)std::max<int64_t>(1, std::min(s, max_s));
     } else {
         p.mapping = 1;
-        p.rows_per_lane = n_i >= (1 << 18) ? 2 : 1;
+        p.rows_per_lane = 1;
         const int64_t wgs = (n_i + p.rows_per_lane * nb::kBlock - 1) / (p.rows_per_lane * nb::kBlock);
         const int64_t target = (int64_t)cus * 8;
         int64_t s = (target + wgs - 1) / wgs;

@@ -83,3 +83,32 @@ def test_gpu_context_refused_without_gfx950():
         pytest.skip("a GPU is present")
     h = C.c_void_p()
     assert nb.lib().nb_ctx_create(C.byref(h), 0, None) == -4
+
+
+def test_argument_validation_adjoint_batched_autotune(host_ctx):
+    L = nb.lib()
+    p = _fake
+    E = -1
+
+    def adj(ctx=host_ctx, n=50, n_i=5, ib=p(4), wa=p(6), gx=p(8)):
+        return L.nb_regular_force_adjoint(ctx, n, p(1), p(2), p(3), n_i, ib, p(5), wa, p(7), gx,
+                                          p(9), p(10), None)
+
+    assert adj(ctx=None) == E and adj(n=0) == E and adj(n_i=-2) == E
+    assert adj(ib=None) == E and adj(wa=None) == E and adj(gx=None) == E
+    assert adj() == -4 and adj(n_i=0, ib=None, wa=None) == -4
+
+    def bat(C=2, j=(0, 10, 30), i=(0, 3, 5), cap=4, prec=1, lst=p(9)):
+        ja = (C_int64 * len(j))(*j)
+        ia = (C_int64 * len(i))(*i)
+        return L.nb_regular_force_batched(host_ctx, C, ja, ia, p(1), p(2), p(3), p(4), p(5), cap,
+                                          prec, p(6), p(7), p(8), lst, p(10), None)
+
+    C_int64 = C.c_int64
+    assert bat() == -4
+    assert bat(C=0) == E and bat(cap=-1) == E and bat(prec=3) == E
+    assert bat(j=(1, 10, 30)) == E and bat(i=(0, 5, 3)) == E and bat(j=(0, 20, 10)) == E
+    assert bat(j=(0, 0, 0)) == E                    # no bodies at all
+    assert bat(lst=None) == E and bat(lst=None, cap=0) == -4
+    assert L.nb_autotune(host_ctx, 10, None, 0) == E
+    assert L.nb_autotune(host_ctx, 4096, None, 0) == -4

@@ -1,0 +1,156 @@
+"""Batched ensemble (one persistent launch over many uneven clusters, replayed
+from a captured HIP graph) against the oracle run cluster by cluster, and
+against single-block launches of the library itself."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1504_03687_amd as nb
+import workloads as W
+from gpu_util import TOL_FP64, TOL_MIXED, check_lists, dev, host, row_rel_err, say
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": TOL_FP64, "mixed": TOL_MIXED}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = nb.Context(0)
+    yield c
+    c.close()
+
+
+def _ensemble(seed=7, sizes=(1, 64, 300, 1000, 2500, 777, 40, 4096, 513, 2, 9000, 130)):
+    rng = np.random.default_rng(seed)
+    xs, vs, ms, blocks, rs2s = [], [], [], [], []
+    j_off, i_off = [0], [0]
+    for c, n in enumerate(sizes):
+        s = W.small_state(200 + c, n, k_nn=min(24, max(n - 1, 1)))
+        ni = 0 if c == 6 else int(rng.integers(1, n + 1))   # one cluster without rows
+        blk = rng.choice(n, ni, replace=False).astype(np.int32)
+        xs.append(s["x"]); vs.append(s["v"]); ms.append(s["m"])
+        blocks.append(blk + j_off[-1]); rs2s.append(s["rs2"][blk])
+        j_off.append(j_off[-1] + n); i_off.append(i_off[-1] + ni)
+    return dict(x=np.concatenate(xs, 1), v=np.concatenate(vs, 1), m=np.concatenate(ms),
+                ib=np.concatenate(blocks).astype(np.int32), rs2=np.concatenate(rs2s),
+                j_off=np.array(j_off), i_off=np.array(i_off))
+
+
+def _oracle_cluster(E, c, cap, rows=None):
+    j0, j1 = E["j_off"][c], E["j_off"][c + 1]
+    r0, r1 = E["i_off"][c], E["i_off"][c + 1]
+    sel = np.arange(r0, r1) if rows is None else rows
+    res = oracle.regular(E["x"][:, j0:j1], E["v"][:, j0:j1], E["m"][j0:j1], E["ib"][sel] - j0,
+                         E["rs2"][sel], cap)
+    lst = np.where(res[3] >= 0, res[3] + j0, res[3])
+    return sel, res[0], res[1], res[2], lst
+
+
+def _check(E, out, cap, tol, rows_per_cluster=None):
+    acc, jerk, cnt, lst, ovf = (host(t) for t in out)
+    worst = 0.0
+    any_ovf = 0
+    for c in range(len(E["j_off"]) - 1):
+        r0, r1 = E["i_off"][c], E["i_off"][c + 1]
+        if r1 == r0:
+            continue
+        rows = None
+        if rows_per_cluster is not None and r1 - r0 > rows_per_cluster:
+            rows = np.random.default_rng(c).choice(np.arange(r0, r1), rows_per_cluster,
+                                                   replace=False)
+        sel, oa, oj, oc, ol = _oracle_cluster(E, c, cap, rows)
+        check_lists(cnt[sel], lst[sel], oc, ol, cap)
+        ea, ej = row_rel_err(acc[:, sel], oa), row_rel_err(jerk[:, sel], oj)
+        worst = max(worst, ea.max(), ej.max())
+        any_ovf |= int((oc > cap).any())
+    assert worst <= tol, worst
+    if rows_per_cluster is None:
+        assert int(ovf[0]) == any_ovf
+    return worst
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("splits", [0, 3])
+def test_batched_small_ensemble(ctx, prec, splits):
+    say(f"batched small {prec} splits={splits}")
+    E = _ensemble()
+    ctx.set_plan(0, 0, splits)
+    try:
+        args = (E["j_off"], E["i_off"], dev(E["x"]), dev(E["v"]), dev(E["m"]), dev(E["ib"]),
+                dev(E["rs2"]))
+        out = nb.regular_force_batched(*args, 20, prec, ctx=ctx)
+        w = _check(E, out, 20, TOL[prec])
+        say(f"  {ctx.last_plan()}  worst err {w:.2e}")
+        # replay of the cached graph gives identical results
+        first = [host(t).copy() for t in out]
+        out2 = nb.regular_force_batched(*args, 20, prec, out=out, ctx=ctx)
+        for p, q in zip(first, out2):
+            assert np.array_equal(p, host(q))
+    finally:
+        ctx.set_plan(0, 0, 0)
+
+
+def test_batched_graph_replay_sees_new_data(ctx):
+    """The graph captures pointers, not values: new positions in the same
+    buffers give the new forces on replay."""
+    say("batched replay with new data")
+    E = _ensemble(seed=9)
+    x, v, m = dev(E["x"]), dev(E["v"]), dev(E["m"])
+    ib, rs2 = dev(E["ib"]), dev(E["rs2"])
+    out = nb.regular_force_batched(E["j_off"], E["i_off"], x, v, m, ib, rs2, 16, "fp64", ctx=ctx)
+    torch.cuda.synchronize()
+    x.mul_(2.0)
+    rs2.mul_(4.0)
+    out = nb.regular_force_batched(E["j_off"], E["i_off"], x, v, m, ib, rs2, 16, "fp64",
+                                   out=out, ctx=ctx)
+    E2 = dict(E, x=2 * E["x"], rs2=4 * E["rs2"])
+    _check(E2, out, 16, TOL_FP64)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_equals_single_launches(ctx, prec):
+    """Each cluster of the batch gives bit-identical rows to a single-block
+    launch of the same plan on that cluster alone."""
+    say(f"batched vs single {prec}")
+    E = _ensemble(seed=11)
+    out = [host(t) for t in nb.regular_force_batched(
+        E["j_off"], E["i_off"], dev(E["x"]), dev(E["v"]), dev(E["m"]), dev(E["ib"]),
+        dev(E["rs2"]), 32, prec, ctx=ctx)]
+    ctx.set_plan(1, 1, 1)
+    try:
+        for c in range(len(E["j_off"]) - 1):
+            j0, j1 = E["j_off"][c], E["j_off"][c + 1]
+            r0, r1 = E["i_off"][c], E["i_off"][c + 1]
+            if r1 == r0:
+                continue
+            single = [host(t) for t in nb.regular_force(
+                dev(E["x"][:, j0:j1]), dev(E["v"][:, j0:j1]), dev(E["m"][j0:j1]),
+                dev(E["ib"][r0:r1] - j0), dev(E["rs2"][r0:r1]), 32, prec, ctx=ctx)]
+            assert np.array_equal(out[0][:, r0:r1], single[0])
+            assert np.array_equal(out[1][:, r0:r1], single[1])
+            assert np.array_equal(out[2][r0:r1], single[2])
+            for b in range(r1 - r0):
+                k = min(int(single[2][b]), 32)
+                assert np.array_equal(out[3][r0 + b, :k], single[3][b, :k] + j0)
+    finally:
+        ctx.set_plan(0, 0, 0)
+
+
+def test_config4_ensemble(ctx):
+    """256 Plummer + Kroupa clusters, N log-uniform in [1024, 32768], active
+    fractions U[0.01, 1]: one persistent launch, sampled rows of every cluster
+    against the oracle."""
+    s = W.config4()
+    say(f"config4: {s['n']} bodies, {s['i_block'].size} rows")
+    xp, vp, _ = nb.predict(dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(s["t0"]),
+                           s["t"], ctx=ctx)
+    ox, ov = oracle.predict(s["t"], s["x"], s["v"], s["a"], s["jk"], s["t0"])
+    E = dict(x=ox, v=ov, m=s["m"], ib=s["i_block"], rs2=s["rs2"], j_off=s["j_off"],
+             i_off=s["i_off"])
+    for prec in ("mixed", "fp64"):
+        out = nb.regular_force_batched(s["j_off"], s["i_off"], xp, vp, dev(s["m"]),
+                                       dev(s["i_block"]), dev(s["rs2"]), s["nb_cap"], prec,
+                                       ctx=ctx)
+        w = _check(E, out, s["nb_cap"], TOL[prec], rows_per_cluster=12)
+        say(f"  {prec}: {ctx.last_plan()}  worst err {w:.2e}")
