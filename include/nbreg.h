@@ -94,10 +94,20 @@ int nb_ctx_set_scratch_limit(nb_ctx *ctx, int64_t bytes);
  * synchronises those events and returns the summed milliseconds and the
  * launch count of one kernel class since the last reset (class 0 = regular
  * force main kernel, 1 = cross-split reduce, 2 = predictor, 3 = adjoint,
- * 4 = batched). */
+ * 4 = batched, 5 = mixed-precision FP64 refinement). */
 int nb_ctx_enable_timing(nb_ctx *ctx, int on);
 int nb_ctx_kernel_time(nb_ctx *ctx, int kernel_class, double *ms, int64_t *launches);
 int nb_ctx_reset_timing(nb_ctx *ctx);
+/* Mixed precision refinement: every NB_MIXED row also accumulates an estimate
+ * of its FP32 rounding error (from the squared norms of its FP32 partial
+ * sums); a row whose estimate times 'safety' exceeds tol times the norm of its
+ * acc or jerk is recomputed in FP64 by a follow-up kernel on the same stream
+ * (forces only; lists are already exact).  Defaults: tol 5e-6, safety 8.
+ * tol = 0 turns the refinement off. */
+int nb_ctx_set_mixed_tolerance(nb_ctx *ctx, double tol, double safety);
+/* Number of rows the last NB_MIXED nb_regular_force call recomputed in FP64
+ * (0 if refinement was off).  Synchronises the context's stream. */
+int nb_ctx_last_refined_rows(nb_ctx *ctx, int32_t *rows);
 
 /* ---- hot path ----------------------------------------------------------- */
 
@@ -127,7 +137,9 @@ int nb_predict(nb_ctx *ctx, int64_t n, double t, const double *x, const double *
  * prec = NB_FP64: all arithmetic in FP64.  prec = NB_MIXED: differences in
  * FP64, then r^-1 (hardware reciprocal square root), r^-2, r^-3 and the force
  * and jerk products in FP32, summed in short FP32 runs folded into FP64
- * running sums, with FP64 cross-split reduction.
+ * running sums, with FP64 cross-split reduction; pairs closer than two
+ * neighbour radii are evaluated in FP64, and rows whose rounding-error
+ * estimate is too large are recomputed in FP64 (nb_ctx_set_mixed_tolerance).
  * Outputs: acc, jerk [3][n_i] FP64; nb_count [n_i] (true count); nb_list
  * [n_i][nb_cap] row-major (first min(count, nb_cap) entries of a row are
  * defined); *overflow (required) = 1 iff some count > nb_cap, else 0;

@@ -30,10 +30,12 @@ __all__ = [
 
 FP64, MIXED = 0, 1
 STATUS_OVERFLOW, STATUS_BAD_INDEX, STATUS_NONFINITE = 1, 2, 4
-CLASS_FORCE, CLASS_MERGE, CLASS_PREDICT, CLASS_ADJOINT, CLASS_BATCHED = range(5)
+CLASS_FORCE, CLASS_MERGE, CLASS_PREDICT, CLASS_ADJOINT, CLASS_BATCHED, CLASS_REDO = range(6)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libnbreg.so")
+# NBREG_LIBRARY may point at another build of the same library (e.g. a
+# variant built for a comparison); the default is the in-tree build.
+_LIB_PATH = os.environ.get("NBREG_LIBRARY") or os.path.join(_HERE, "libnbreg.so")
 _lib = None
 _lock = threading.Lock()
 
@@ -75,6 +77,8 @@ def lib() -> C.CDLL:
             "nb_ctx_enable_timing": ([vp, C.c_int], C.c_int),
             "nb_ctx_kernel_time": ([vp, C.c_int, C.POINTER(dbl), C.POINTER(i64)], C.c_int),
             "nb_ctx_reset_timing": ([vp], C.c_int),
+            "nb_ctx_set_mixed_tolerance": ([vp, dbl, dbl], C.c_int),
+            "nb_ctx_last_refined_rows": ([vp, C.POINTER(i32)], C.c_int),
             "nb_predict": ([vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "nb_regular_force": ([vp, i64, vp, vp, vp, i32, vp, vp, i32, C.c_int, vp, vp, vp,
                                   vp, vp, u32p], C.c_int),
@@ -160,6 +164,19 @@ class Context:
 
     def reset_timing(self):
         _check(lib().nb_ctx_reset_timing(self._h), "nb_ctx_reset_timing")
+
+    def set_mixed_tolerance(self, tol: float = 5e-6, safety: float = 8.0):
+        """Target per-row relative error of NB_MIXED and the safety factor of
+        its rounding-error estimate; rows above it are recomputed in FP64
+        (tol = 0: never)."""
+        _check(lib().nb_ctx_set_mixed_tolerance(self._h, float(tol), float(safety)),
+               "nb_ctx_set_mixed_tolerance")
+
+    def last_refined_rows(self) -> int:
+        """Rows the last mixed call recomputed in FP64 (synchronises)."""
+        k = C.c_int32()
+        _check(lib().nb_ctx_last_refined_rows(self._h, C.byref(k)), "nb_ctx_last_refined_rows")
+        return k.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -10,7 +10,7 @@
 #include <cstring>
 #include <vector>
 
-#include "../../include/nbreg.h"
+#include "nbreg.h"
 #include "nb_runtime.h"
 
 namespace nbrt {

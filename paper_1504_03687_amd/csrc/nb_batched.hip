@@ -17,7 +17,7 @@
 #include <numeric>
 #include <vector>
 
-#include "../../include/nbreg.h"
+#include "nbreg.h"
 #include "nb_rows.h"
 #include "nb_runtime.h"
 
@@ -117,6 +117,7 @@ struct BatchedCache {
     int prec = 0;
     int rows_per_lane = 1;
     int forced_splits = 0;
+    double redo_k = 0.0;
     const void *ptrs[11] = {};
     // device state
     void *dmem = nullptr;
@@ -216,7 +217,8 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     const size_t b_it = r256(std::max<size_t>(1, it_dev.size()) * sizeof(nb::BItem));
     const size_t b_mr = r256(std::max<size_t>(1, merge_rows.size()) * sizeof(int32_t));
     const size_t b_slots = nb::slot_scratch_bytes(slots);
-    const size_t total = b_queue + b_cl + 2 * b_mr + b_it + b_slots;
+    const size_t b_redo = c->redo_k > 0.0 ? nb::redo_scratch_bytes(f.n_i) : 0;
+    const size_t total = b_queue + b_cl + 2 * b_mr + b_it + b_slots + b_redo;
     if (ctx->scratch_limit && total > ctx->scratch_limit) return NB_ERR_OOM;
     hipError_t e = hipMalloc(&c->dmem, total);
     if (e != hipSuccess) {
@@ -236,6 +238,8 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     int32_t *drc = (int32_t *)p;
     p += b_mr;
     void *dslots = p;
+    p += b_slots;
+    void *dredo = p;
 
     e = hipMemcpy(dcl, cl.data(), cl.size() * sizeof(nb::BCluster), hipMemcpyHostToDevice);
     if (e == hipSuccess && !it_dev.empty())
@@ -253,6 +257,8 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     nb::BatchArgs &A = c->args;
     A.f = f;
     nb::bind_slot_scratch(A.f, slots, dslots);
+    A.f.redo_k = c->redo_k;
+    if (c->redo_k > 0.0) nb::bind_redo_scratch(A.f, dredo);
     A.f.splits = 0;          // per-cluster
     A.f.split_len = 0;
     A.clusters = dcl;
@@ -274,8 +280,12 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     if (e == hipSuccess) {
         hipError_t le = nb::launch_fill_i32(queue, 0, 1, cs);
         if (le == hipSuccess) le = nb::launch_fill_i32(f.overflow, 0, 1, cs);
+        if (le == hipSuccess && c->redo_k > 0.0)
+            le = nb::launch_fill_i32(A.f.redo_count, 0, 1, cs);
         if (le == hipSuccess) le = nb::launch_batched(mixed, c->rows_per_lane, c->grid, A, cs);
         if (le == hipSuccess) le = nb::launch_batched_merge(A, cs);
+        if (le == hipSuccess && c->redo_k > 0.0)
+            le = nb::launch_redo(A.f, ctx->cu_count, cs);
         e = hipStreamEndCapture(cs, &c->graph);
         if (e == hipSuccess) e = le;
     }
@@ -315,12 +325,14 @@ extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const i
     const bool mixed = prec == NB_MIXED;
     const int rpl = (ctx->has_forced && ctx->forced.rows_per_lane == 2) ? 2 : 1;
     const int fsplits = ctx->has_forced ? ctx->forced.splits : 0;
+    const double rk = mixed ? redo_k(ctx) : 0.0;
     const void *ptrs[11] = {xp, vp, m, i_block, rs2, acc, jerk, nb_count, nb_list, overflow,
                             status};
     BatchedCache *hit = nullptr;
     for (auto *c : ctx->batched) {
         if (c->cap == nb_cap && c->prec == (int)prec && c->rows_per_lane == rpl &&
-            c->forced_splits == fsplits && (int32_t)c->j_off.size() == n_clusters + 1 &&
+            c->forced_splits == fsplits && c->redo_k == rk &&
+            (int32_t)c->j_off.size() == n_clusters + 1 &&
             std::memcmp(c->ptrs, ptrs, sizeof ptrs) == 0 &&
             std::equal(c->j_off.begin(), c->j_off.end(), j_off_host) &&
             std::equal(c->i_off.begin(), c->i_off.end(), i_off_host)) {
@@ -346,6 +358,7 @@ extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const i
         c->prec = (int)prec;
         c->rows_per_lane = rpl;
         c->forced_splits = fsplits;
+        c->redo_k = rk;
         std::memcpy(c->ptrs, ptrs, sizeof ptrs);
         nb::ForceArgs f{};
         f.n = n;
@@ -371,6 +384,7 @@ extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const i
         hit = c;
     }
     hit->last_use = ++g_use_clock;
+    ctx->last_redo_counter = hit->redo_k > 0.0 ? hit->args.f.redo_count : nullptr;
     std::snprintf(ctx->last_plan, sizeof ctx->last_plan,
                   "batched clusters=%d items=%d grid=%d rows_per_lane=%d merge_rows=%d prec=%s",
                   n_clusters, hit->args.n_items, hit->grid, hit->rows_per_lane,

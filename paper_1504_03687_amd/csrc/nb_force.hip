@@ -22,6 +22,8 @@
 // list in ascending j.  No floating-point atomics are used anywhere, so each
 // plan is bitwise deterministic and a row's result does not depend on the
 // other rows of the block.
+#include <algorithm>
+
 #include "nb_rows.h"
 
 namespace nb {
@@ -165,10 +167,12 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
         T.jx = wave_sum(T.jx);
         T.jy = wave_sum(T.jy);
         T.jz = wave_sum(T.jz);
+        T.va = wave_sum(T.va);
+        T.vj = wave_sum(T.vj);
         const int64_t b = group * G + g;
         if (lane == 0 && b < a.n_i) {
             bool o = false, bd = false, f = false;
-            row_store<MIXED>(a, b, d, ri[g] >= 0, T, cnt[g], o, bd, f);
+            row_store<MIXED>(a, b, d, ri[g] >= 0, T, cnt[g], o, bd, f, j0, j1);
             ovf |= o;
             bad |= bd;
             nonfin |= f;
@@ -187,6 +191,16 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(ForceArgs a)
     merge_row(a, b, g);
 }
 
+// Persistent waves over the redo list.
+__global__ __launch_bounds__(kBlock) void redo_kernel(ForceArgs a)
+{
+    const int32_t gw = (int32_t)(blockIdx.x * (kBlock / kWave)) +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int32_t nw = (int32_t)(gridDim.x * (kBlock / kWave));
+    const int32_t count = __builtin_amdgcn_readfirstlane(*(volatile int32_t *)a.redo_count);
+    for (int32_t q = gw; q < count; q += nw) redo_row(a, q);
+}
+
 __global__ void fill_i32_kernel(int32_t *p, int32_t value, int64_t count)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,8 +215,33 @@ size_t slot_scratch_bytes(int64_t slots)
 {
     if (slots <= 0) return 0;
     const size_t s = (size_t)slots;
-    return round256(s * 6 * sizeof(double)) + round256(s * sizeof(int32_t)) +
+    return round256(s * kSlotComp * sizeof(double)) + round256(s * sizeof(int32_t)) +
            round256(s * kSegCap * sizeof(int32_t));
+}
+
+size_t redo_scratch_bytes(int32_t n_i)
+{
+    return 256 + 3 * round256((size_t)(n_i > 0 ? n_i : 1) * sizeof(int32_t));
+}
+
+void bind_redo_scratch(ForceArgs &a, void *base)
+{
+    char *p = (char *)base;
+    const size_t arr = round256((size_t)(a.n_i > 0 ? a.n_i : 1) * sizeof(int32_t));
+    a.redo_count = (int32_t *)p;
+    a.redo_rows = (int32_t *)(p + 256);
+    a.redo_j0 = (int32_t *)(p + 256 + arr);
+    a.redo_j1 = (int32_t *)(p + 256 + 2 * arr);
+}
+
+hipError_t launch_redo(const ForceArgs &a, int cu_count, hipStream_t s)
+{
+    const int64_t waves = std::min<int64_t>((int64_t)(cu_count > 0 ? cu_count : 256) * 16,
+                                            (a.n_i + 0) > 0 ? a.n_i : 1);
+    const int64_t per = kBlock / kWave;
+    hipLaunchKernelGGL(redo_kernel, dim3((unsigned)((waves + per - 1) / per)), dim3(kBlock), 0, s,
+                       a);
+    return hipGetLastError();
 }
 
 void bind_slot_scratch(ForceArgs &a, int64_t slots, void *base)
@@ -217,7 +256,7 @@ void bind_slot_scratch(ForceArgs &a, int64_t slots, void *base)
     const size_t s = (size_t)slots;
     char *p = (char *)base;
     a.part = (double *)p;
-    p += round256(s * 6 * sizeof(double));
+    p += round256(s * kSlotComp * sizeof(double));
     a.seg_cnt = (int32_t *)p;
     p += round256(s * sizeof(int32_t));
     a.seg_list = (int32_t *)p;

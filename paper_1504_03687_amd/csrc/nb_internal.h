@@ -47,12 +47,26 @@ struct ForceArgs {
     int32_t splits;
     int64_t split_len;
     // scratch (splits > 1): one slot per (row, split), slot = split * n_i + b;
-    // part [6][total_slots], seg_cnt [total_slots], seg_list [total_slots][kSegCap]
+    // part [kSlotComp][total_slots], seg_cnt [total_slots],
+    // seg_list [total_slots][kSegCap]
     int64_t total_slots;
     double *part;
     int32_t *seg_cnt;
     int32_t *seg_list;
+    // mixed precision: rows whose estimated error is too large are appended
+    // (row, j-range) to the redo list and recomputed in FP64 afterwards
+    double redo_k;        // 2^-24 * safety / tolerance; 0 disables
+    int32_t *redo_count;  // device counter, zeroed before the force kernel
+    int32_t *redo_rows;   // [n_i]
+    int32_t *redo_j0, *redo_j1;
 };
+
+// Components per slot: acc x,y,z, jerk x,y,z, and the two error-scale sums.
+constexpr int kSlotComp = 8;
+// Extra scratch for the redo list of n_i rows (counter + 3 int arrays).
+size_t redo_scratch_bytes(int32_t n_i);
+void bind_redo_scratch(ForceArgs &a, void *base);
+hipError_t launch_redo(const ForceArgs &a, int cu_count, hipStream_t s);
 
 struct Plan {
     int mapping;        // 1 = row per lane (LDS j-tiles), 2 = row group per wave

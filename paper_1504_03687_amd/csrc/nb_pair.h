@@ -47,26 +47,44 @@ struct Sums;
 template <>
 struct Sums<false> {
     double ax, ay, az, jx, jy, jz;
-    __device__ __forceinline__ void zero() { ax = ay = az = jx = jy = jz = 0.0; }
+    double va, vj;   // unused in FP64 (kept for a common slot layout)
+    __device__ __forceinline__ void zero() { ax = ay = az = jx = jy = jz = va = vj = 0.0; }
     __device__ __forceinline__ void fold() {}
 };
 
+// va, vj: sums of the squared norms of the folded FP32 partials.  For terms of
+// varying sign this estimates sum |term|^2, the scale of the accumulated FP32
+// rounding error of the row (which grows like its square root); rows whose
+// estimated relative error is too large are recomputed in FP64.
 template <>
 struct Sums<true> {
     double ax, ay, az, jx, jy, jz;
+    double va, vj;
     float pax, pay, paz, pjx, pjy, pjz;
     __device__ __forceinline__ void zero()
     {
-        ax = ay = az = jx = jy = jz = 0.0;
+        ax = ay = az = jx = jy = jz = va = vj = 0.0;
         pax = pay = paz = pjx = pjy = pjz = 0.0f;
     }
     __device__ __forceinline__ void fold()
     {
         ax += (double)pax; ay += (double)pay; az += (double)paz;
         jx += (double)pjx; jy += (double)pjy; jz += (double)pjz;
+        va += (double)__builtin_fmaf(paz, paz, __builtin_fmaf(pay, pay, pax * pax));
+        vj += (double)__builtin_fmaf(pjz, pjz, __builtin_fmaf(pjy, pjy, pjx * pjx));
         pax = pay = paz = pjx = pjy = pjz = 0.0f;
     }
 };
+
+// True when a mixed row should be recomputed in FP64: the rounding-error
+// estimate k * sqrt(v) exceeds |sum| for acc or jerk (k = 2^-24 * safety / tol).
+__device__ __forceinline__ bool needs_redo(double k, double ax, double ay, double az, double jx,
+                                           double jy, double jz, double va, double vj)
+{
+    const double na2 = ax * ax + ay * ay + az * az;
+    const double nj2 = jx * jx + jy * jy + jz * jz;
+    return k * k * va > na2 || k * k * vj > nj2;
+}
 
 // FP64 regular term.  r2 is the FP64 squared distance; 'excl' marks the self
 // pair or a neighbour (the term is then exactly zero: r^-1 is selected to 0).

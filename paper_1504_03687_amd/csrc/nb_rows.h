@@ -148,11 +148,22 @@ __device__ __forceinline__ void load_body(JBody &J, const ForceArgs &a, int64_t 
     J.pad = 0;
 }
 
+// Appends row b (with its j-range) to the FP64 redo list.
+__device__ __forceinline__ void redo_push(const ForceArgs &a, int64_t b, int64_t j0, int64_t j1)
+{
+    const int32_t q = atomicAdd(a.redo_count, 1);
+    a.redo_rows[q] = (int32_t)b;
+    a.redo_j0[q] = (int32_t)j0;
+    a.redo_j1[q] = (int32_t)j1;
+}
+
 // One row's final sums and count: to the outputs, or to its split slot.
+// [j0, j1) is the row's whole j-range when the destination is direct.
 template <bool MIXED>
 __device__ __forceinline__ void row_store(const ForceArgs &a, int64_t b, const Dest &d,
                                           bool valid, const Sums<MIXED> &S, int32_t cnt,
-                                          bool &ovf, bool &bad, bool &nonfin)
+                                          bool &ovf, bool &bad, bool &nonfin, int64_t j0,
+                                          int64_t j1)
 {
     if (d.direct) {
         if (!valid) {
@@ -171,6 +182,9 @@ __device__ __forceinline__ void row_store(const ForceArgs &a, int64_t b, const D
         a.nb_count[b] = cnt;
         ovf = cnt > a.cap;
         nonfin = !finite6(S.ax, S.ay, S.az, S.jx, S.jy, S.jz);
+        if (MIXED && a.redo_k > 0.0 &&
+            needs_redo(a.redo_k, S.ax, S.ay, S.az, S.jx, S.jy, S.jz, S.va, S.vj))
+            redo_push(a, b, j0, j1);
     } else {
         const int64_t slot = dest_slot(d, b);
         double *p = a.part + slot;
@@ -181,6 +195,8 @@ __device__ __forceinline__ void row_store(const ForceArgs &a, int64_t b, const D
         p[3 * T] = S.jx;
         p[4 * T] = S.jy;
         p[5 * T] = S.jz;
+        p[6 * T] = S.va;
+        p[7 * T] = S.vj;
         a.seg_cnt[slot] = cnt;
     }
 }
@@ -245,7 +261,7 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTil
         const int64_t b = row0 + r * kBlock + tid;
         if (b < row_end) {
             bool o = false, bd = false, f = false;
-            row_store<MIXED>(a, b, d, R[r].i >= 0, R[r].S, R[r].cnt, o, bd, f);
+            row_store<MIXED>(a, b, d, R[r].i >= 0, R[r].S, R[r].cnt, o, bd, f, j0, j1);
             ovf |= o;
             bad |= bd;
             nonfin |= f;
@@ -281,14 +297,14 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
     const int32_t S = g.splits;
     const int64_t T = a.total_slots;
 
-    double v[6] = {0, 0, 0, 0, 0, 0};
+    double v[kSlotComp] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int32_t s = lane; s < S; s += kWave) {
         const double *p = a.part + g.slot0 + (int64_t)s * g.slot_step;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) v[k] += p[(int64_t)k * T];
+        for (int k = 0; k < kSlotComp; ++k) v[k] += p[(int64_t)k * T];
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+    for (int k = 0; k < kSlotComp; ++k) v[k] = wave_sum(v[k]);
 
     bool ovf = false, nonfin = false;
     if (bad) {
@@ -360,9 +376,55 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
             a.nb_count[b] = (int32_t)off;
             ovf = off > a.cap;
             nonfin = !finite6(v[0], v[1], v[2], v[3], v[4], v[5]);
+            if (a.redo_k > 0.0 && needs_redo(a.redo_k, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]))
+                redo_push(a, b, g.j_begin, g.j_end);
         }
     }
     flush_flags(a, ovf, bad && lane == 0, nonfin);
+}
+
+// FP64 recompute of one listed row by one whole wave (j spread over lanes):
+// forces only; the neighbour list and count of the row are already final.
+__device__ __forceinline__ void redo_row(const ForceArgs &a, int32_t q)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t b = a.redo_rows[q];
+    const int64_t j0 = a.redo_j0[q], j1 = a.redo_j1[q];
+    const int64_t i = a.i_block[b];
+    const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
+    const double vxi = a.vp[i], vyi = a.vp[a.n + i], vzi = a.vp[2 * a.n + i];
+    const float rs2f = (float)a.rs2[b];
+    const double hi = cand_bound_f64(rs2f);
+    Sums<false> S;
+    S.zero();
+    for (int64_t base = j0; base < j1; base += kWave) {
+        const int64_t j = base + lane;
+        JBody J;
+        load_body(J, a, j, j1);
+        const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        bool excl = false;
+        if (r2 < hi) {
+            double ex = dx, ey = dy, ez = dz;
+            opaque(ex, ey, ez);
+            excl = j == i || canon_r2f(ex, ey, ez) < rs2f;
+        }
+        accum_f64(S, dx, dy, dz, r2, J.vx - vxi, J.vy - vyi, J.vz - vzi, J.m, excl);
+    }
+    S.ax = wave_sum(S.ax);
+    S.ay = wave_sum(S.ay);
+    S.az = wave_sum(S.az);
+    S.jx = wave_sum(S.jx);
+    S.jy = wave_sum(S.jy);
+    S.jz = wave_sum(S.jz);
+    if (lane == 0) {
+        a.acc[b] = S.ax;
+        a.acc[a.n_i + b] = S.ay;
+        a.acc[2 * (int64_t)a.n_i + b] = S.az;
+        a.jerk[b] = S.jx;
+        a.jerk[a.n_i + b] = S.jy;
+        a.jerk[2 * (int64_t)a.n_i + b] = S.jz;
+    }
 }
 
 }  // namespace nb

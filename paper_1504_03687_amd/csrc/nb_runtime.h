@@ -8,7 +8,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/nbreg.h"
+#include "nbreg.h"
 #include "nb_internal.h"
 
 enum {
@@ -17,7 +17,8 @@ enum {
     NB_CLASS_PREDICT = 2,
     NB_CLASS_ADJOINT = 3,
     NB_CLASS_BATCHED = 4,
-    NB_NCLASS = 5
+    NB_CLASS_REDO = 5,
+    NB_NCLASS = 6
 };
 
 namespace nbrt {
@@ -44,12 +45,17 @@ struct nb_ctx {
     bool has_forced = false;
     char last_plan[256] = "none";
     std::map<std::tuple<int, int64_t, int64_t>, nb::Plan> tuned;
+    // mixed precision: target relative error per row and safety factor of
+    // the rounding-error estimate that triggers an FP64 recompute (tol 0: off)
+    double mixed_tol = 5e-6;
+    double mixed_safety = 8.0;
     // timing
     bool timing = false;
     std::vector<nbrt::PendingTiming> pending;
     std::vector<hipEvent_t> free_events;
-    double ms[NB_NCLASS] = {0, 0, 0, 0, 0};
-    int64_t launches[NB_NCLASS] = {0, 0, 0, 0, 0};
+    double ms[NB_NCLASS] = {};
+    int64_t launches[NB_NCLASS] = {};
+    int32_t *last_redo_counter = nullptr;   // device counter of the last mixed call
     // batched entry point: cached device metadata and graphs per shape
     std::vector<nbrt::BatchedCache *> batched;
 };
@@ -60,6 +66,7 @@ int ensure_scratch(nb_ctx *ctx, size_t bytes);
 hipError_t timed_begin(nb_ctx *ctx, int cls, hipEvent_t *ev);
 hipError_t timed_end(nb_ctx *ctx, int cls, hipEvent_t *ev);
 int64_t bucket_log2(int64_t v);
+double redo_k(const nb_ctx *ctx);
 nb::Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed);
 void finish_plan(nb::Plan &p, int64_t n, int32_t n_i, int64_t *split_len);
 }  // namespace nbrt

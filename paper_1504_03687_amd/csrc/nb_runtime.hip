@@ -18,7 +18,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/nbreg.h"
+#include "nbreg.h"
 #include "nb_internal.h"
 #include "nb_runtime.h"
 
@@ -84,6 +84,12 @@ hipError_t timed_end(nb_ctx *ctx, int cls, hipEvent_t *ev)
     if (e != hipSuccess) return e;
     ctx->pending.push_back({cls, ev[0], ev[1]});
     return hipSuccess;
+}
+
+double redo_k(const nb_ctx *ctx)
+{
+    if (!(ctx->mixed_tol > 0.0)) return 0.0;
+    return 0x1p-24 * ctx->mixed_safety / ctx->mixed_tol;
 }
 
 int64_t bucket_log2(int64_t v)
@@ -349,11 +355,19 @@ int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
     fa.status = status;
     fa.splits = p.splits;
     fa.split_len = split_len;
-    if (p.splits > 1) {
-        int rc = ensure_scratch(ctx, nb::force_scratch_bytes(p, n_i));
+    fa.redo_k = mixed ? redo_k(ctx) : 0.0;
+    const size_t redo_bytes = fa.redo_k > 0.0 ? nb::redo_scratch_bytes(n_i) : 0;
+    const size_t slot_bytes = nb::force_scratch_bytes(p, n_i);
+    if (redo_bytes + slot_bytes > 0) {
+        int rc = ensure_scratch(ctx, redo_bytes + slot_bytes);
         if (rc != NB_OK) return rc;
     }
-    nb::force_bind_scratch(fa, ctx->scratch);
+    if (redo_bytes) {
+        nb::bind_redo_scratch(fa, ctx->scratch);
+        e = hipMemsetAsync(fa.redo_count, 0, sizeof(int32_t), ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e);
+    }
+    nb::force_bind_scratch(fa, (char *)ctx->scratch + redo_bytes);
     std::snprintf(ctx->last_plan, sizeof ctx->last_plan,
                   "mapping=%d rows_per_lane=%d splits=%d split_len=%lld prec=%s", p.mapping,
                   p.rows_per_lane, p.splits, (long long)split_len, mixed ? "mixed" : "fp64");
@@ -369,7 +383,35 @@ int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
         if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_MERGE, ev);
         if (e != hipSuccess) return hip_fail(ctx, e);
     }
+    if (redo_bytes) {
+        e = timed_begin(ctx, NB_CLASS_REDO, ev);
+        if (e == hipSuccess) e = nb::launch_redo(fa, ctx->cu_count, ctx->stream);
+        if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_REDO, ev);
+        if (e != hipSuccess) return hip_fail(ctx, e);
+        ctx->last_redo_counter = fa.redo_count;
+    } else {
+        ctx->last_redo_counter = nullptr;
+    }
     return NB_OK;
+}
+
+int nb_ctx_set_mixed_tolerance(nb_ctx *ctx, double tol, double safety)
+{
+    if (!ctx || !(tol >= 0.0) || !(safety > 0.0)) return NB_ERR_INVALID_ARG;
+    ctx->mixed_tol = tol;
+    ctx->mixed_safety = safety;
+    return NB_OK;
+}
+
+int nb_ctx_last_refined_rows(nb_ctx *ctx, int32_t *rows)
+{
+    if (!ctx || !rows) return NB_ERR_INVALID_ARG;
+    *rows = 0;
+    if (!ctx->usable || !ctx->last_redo_counter) return NB_OK;
+    hipError_t e = hipMemcpyAsync(rows, ctx->last_redo_counter, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
 }
 
 int nb_regular_force_adjoint(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,

@@ -126,7 +126,7 @@ def test_batched_equals_single_launches(ctx, prec):
                 continue
             single = [host(t) for t in nb.regular_force(
                 dev(E["x"][:, j0:j1]), dev(E["v"][:, j0:j1]), dev(E["m"][j0:j1]),
-                dev(E["ib"][r0:r1] - j0), dev(E["rs2"][r0:r1]), 32, prec, ctx=ctx)]
+                dev((E["ib"][r0:r1] - j0).astype(np.int32)), dev(E["rs2"][r0:r1]), 32, prec, ctx=ctx)]
             assert np.array_equal(out[0][:, r0:r1], single[0])
             assert np.array_equal(out[1][:, r0:r1], single[1])
             assert np.array_equal(out[2][r0:r1], single[2])
