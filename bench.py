@@ -54,6 +54,9 @@ def main():
                     help="rows of the full block timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-levels", action="store_true")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (FP64 elementwise kernel) "
+                         "and print its bandwidth; used to scale rocprofv3 byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -61,6 +64,22 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        reps = 5
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / reps
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                          "launches": reps + 1, "GB_per_s": round(2 * n * 8 / dt * 1e-9, 1)}))
+        return
 
     import paper_1504_03687_amd as nb
     import workloads as W
@@ -106,11 +125,14 @@ def main():
         kms, kl = ctx.kernel_time(nb.CLASS_FORCE)
         mms, ml = ctx.kernel_time(nb.CLASS_MERGE)
         pms, pl = ctx.kernel_time(nb.CLASS_PREDICT)
+        rms, rl = ctx.kernel_time(nb.CLASS_REDO)
         ctx.enable_timing(False)
+        refined = ctx.last_refined_rows() if prec == "mixed" else 0
         ms_step = (t2 - t1) * 1e3 / args.steps
         res[prec] = dict(ms_per_step=ms_step, pairs_per_s=pairs / (ms_step * 1e-3),
                          force_kernel_ms=kms / max(kl, 1), merge_kernel_ms=mms / max(ml, 1),
-                         predict_kernel_ms=pms / max(pl, 1), plan=ctx.last_plan(),
+                         predict_kernel_ms=pms / max(pl, 1), refine_kernel_ms=rms / max(rl, 1),
+                         refined_rows=refined, plan=ctx.last_plan(),
                          overflow=int(out[4].item()))
         log(f"{prec}: {ms_step:.2f} ms/step, {pairs / ms_step * 1e-6:.1f} G pairs/s, "
             f"force kernel {res[prec]['force_kernel_ms']:.2f} ms, plan {ctx.last_plan()}")
@@ -199,6 +221,8 @@ def main():
                            "force_kernel_ms": round(r["force_kernel_ms"], 3),
                            "merge_kernel_ms": round(r["merge_kernel_ms"], 3),
                            "predict_kernel_ms": round(r["predict_kernel_ms"], 4),
+                           "refine_kernel_ms": round(r["refine_kernel_ms"], 3),
+                           "refined_rows": r["refined_rows"],
                            "plan": r["plan"], "overflow": r["overflow"]}
                        for p, r in res.items()},
         "levels": levels,

@@ -102,7 +102,7 @@ int nb_ctx_reset_timing(nb_ctx *ctx);
  * of its FP32 rounding error (from the squared norms of its FP32 partial
  * sums); a row whose estimate times 'safety' exceeds tol times the norm of its
  * acc or jerk is recomputed in FP64 by a follow-up kernel on the same stream
- * (forces only; lists are already exact).  Defaults: tol 5e-6, safety 8.
+ * (forces only; lists are already exact).  Defaults: tol 5e-6, safety 32.
  * tol = 0 turns the refinement off. */
 int nb_ctx_set_mixed_tolerance(nb_ctx *ctx, double tol, double safety);
 /* Number of rows the last NB_MIXED nb_regular_force call recomputed in FP64

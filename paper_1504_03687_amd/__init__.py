@@ -165,7 +165,7 @@ class Context:
     def reset_timing(self):
         _check(lib().nb_ctx_reset_timing(self._h), "nb_ctx_reset_timing")
 
-    def set_mixed_tolerance(self, tol: float = 5e-6, safety: float = 8.0):
+    def set_mixed_tolerance(self, tol: float = 5e-6, safety: float = 32.0):
         """Target per-row relative error of NB_MIXED and the safety factor of
         its rounding-error estimate; rows above it are recomputed in FP64
         (tol = 0: never)."""

@@ -239,7 +239,7 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTil
         if (t + 1 < ntiles) load_body(nxt, a, tbase + kTile + tid, j1);
         const JBody *buf = tile[cur];
         for (int jj = 0; jj < kTile; jj += kFold) {
-#pragma unroll 4
+#pragma unroll 2
             for (int q = 0; q < kFold; ++q) {
                 const JBody &J = buf[jj + q];
                 const int32_t jidx = (int32_t)(tbase + jj + q);

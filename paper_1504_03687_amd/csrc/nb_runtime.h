@@ -48,7 +48,7 @@ struct nb_ctx {
     // mixed precision: target relative error per row and safety factor of
     // the rounding-error estimate that triggers an FP64 recompute (tol 0: off)
     double mixed_tol = 5e-6;
-    double mixed_safety = 8.0;
+    double mixed_safety = 32.0;
     // timing
     bool timing = false;
     std::vector<nbrt::PendingTiming> pending;
