@@ -94,7 +94,8 @@ int nb_ctx_set_scratch_limit(nb_ctx *ctx, int64_t bytes);
  * synchronises those events and returns the summed milliseconds and the
  * launch count of one kernel class since the last reset (class 0 = regular
  * force main kernel, 1 = cross-split reduce, 2 = predictor, 3 = adjoint,
- * 4 = batched, 5 = mixed-precision FP64 refinement). */
+ * 4 = batched, 5 = mixed-precision FP64 refinement, 6 = irregular force
+ * and potential). */
 int nb_ctx_enable_timing(nb_ctx *ctx, int on);
 int nb_ctx_kernel_time(nb_ctx *ctx, int kernel_class, double *ms, int64_t *launches);
 int nb_ctx_reset_timing(nb_ctx *ctx);
@@ -192,6 +193,41 @@ int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const int64_t *j_o
  * the table is loaded from it instead (flags & 1 forces re-tuning); after
  * tuning the table is written there.  Synchronises the device. */
 int nb_autotune(nb_ctx *ctx, int64_t n, const char *cache_path, int flags);
+
+/* ---- the rest of the block step ---------------------------------------- */
+
+/* Irregular force + jerk (section 2: the irregular force sums only the
+ * neighbours): for row b with body i = i_block[b], the same pair terms as
+ * nb_regular_force summed over the first min(nb_count[b], nb_cap) entries of
+ * row b of nb_list ([n_i][nb_cap], as written by nb_regular_force).  FP64.
+ * acc, jerk: [3][n_i].  Entries outside [0, n) or equal to i are skipped and
+ * set NB_STATUS_BAD_INDEX; a bad i_block entry gives a zero row.  With the
+ * lists of a regular-force call on the same state, regular + irregular is the
+ * full Newtonian force and jerk. */
+int nb_irregular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                       const double *m, int32_t n_i, const int32_t *i_block, int32_t nb_cap,
+                       const int32_t *nb_count, const int32_t *nb_list, double *acc,
+                       double *jerk, uint32_t *status);
+
+/* Fourth-order Hermite corrector of the integrator (section 2), entry-wise
+ * over n entries with step h[n] (all other arrays [3][n] planes, FP64):
+ *   v1 = v0 + h/2 (a0 + a1) + h^2/12 (j0 - j1)
+ *   x1 = x0 + h/2 (v0 + v1) + h^2/12 (a0 - a1)
+ *   a3 = (12 (a0 - a1) + 6 h (j0 + j1)) / h^3
+ *   a2 = (-6 (a0 - a1) - h (4 j0 + 2 j1)) / h^2 + h a3   (second derivative at
+ *        the end of the step)
+ * where a0, j0 are the force and jerk at the start of the step and a1, j1 at
+ * its end (evaluated on the predicted state).  Outputs may alias x0 / v0. */
+int nb_hermite_correct(nb_ctx *ctx, int64_t n, const double *h, const double *x0,
+                       const double *v0, const double *a0, const double *j0, const double *a1,
+                       const double *j1, double *x1, double *v1, double *a2, double *a3);
+
+/* Potential (section 3.2.1; used for the energy check and the scaling to
+ * N-body units, section 3.3.2): phi[i] = -sum_{j != i} m_j / |x_j - x_i|
+ * (x: [3][n] plane, FP64) and, if energy is not NULL, *energy (one device
+ * double) = 1/2 sum_i m_i phi_i, reduced in a fixed order. */
+int nb_potential(nb_ctx *ctx, int64_t n, const double *x, const double *m, double *phi,
+                 double *energy);
 
 #ifdef __cplusplus
 }

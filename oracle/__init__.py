@@ -16,6 +16,8 @@ Parity status per function (what pins it; see tests/test_oracle_pins.py):
   potential        -- two-body closed form, Plummer energy -1/2 (pinned)
   adjoint          -- central differences of local losses (pinned)
   local_loss       -- linear in m; equals the sum of pair losses (pinned)
+  hermite_correct  -- exact for cubic force histories, two-body orbit
+                      convergence at fourth order (pinned)
 """
 from __future__ import annotations
 
@@ -64,6 +66,8 @@ def lib():
         L.or_adjoint.restype = None
         L.or_local_loss.argtypes = [i64, _D, _D, _D, _D, i32, _I, _D, _D, _D, i64]
         L.or_local_loss.restype = dbl
+        L.or_hermite_correct.argtypes = [i64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.or_hermite_correct.restype = None
         _lib = L
     return _lib
 
@@ -146,3 +150,12 @@ def local_loss(xp, vp, m, i_block, rs2, w_a, w_j, body, xm=None):
     i_block = _i32(i_block)
     return lib().or_local_loss(m.size, xp, vp, m, xm, i_block.size, i_block, rs2, w_a,
                                w_j, int(body))
+
+
+def hermite_correct(h, x0, v0, a0, j0, a1, j1):
+    """Fourth-order Hermite corrector: (x1, v1, a2 at the step end, a3)."""
+    h, x0, v0, a0, j0, a1, j1 = map(_f64, (h, x0, v0, a0, j0, a1, j1))
+    n = h.size
+    out = [np.empty((3, n)) for _ in range(4)]
+    lib().or_hermite_correct(n, h, x0, v0, a0, j0, a1, j1, *out)
+    return tuple(out)

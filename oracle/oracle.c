@@ -388,4 +388,38 @@ double or_local_loss(int64_t n, const double *xp, const double *vp, const double
     return cs_get(&L);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Fourth-order Hermite corrector (the integrator of section 2, after Makino  */
+/* 1991): with the force a0 and its derivative j0 at the start of a step of   */
+/* length h and the new a1, j1 at its end (evaluated at the predicted state), */
+/*   v1 = v0 + h/2 (a0 + a1) + h^2/12 (j0 - j1)                                */
+/*   x1 = x0 + h/2 (v0 + v1) + h^2/12 (a0 - a1)                                */
+/* and the second and third force derivatives at the end of the step from the */
+/* cubic Hermite interpolant of a over the step:                              */
+/*   a2(t0) = (-6 (a0 - a1) - h (4 j0 + 2 j1)) / h^2                           */
+/*   a3     = (12 (a0 - a1) + 6 h (j0 + j1)) / h^3                             */
+/*   a2(t1) = a2(t0) + h a3                                                    */
+/* All [3][n] planes, per-body step h[n].                                      */
+/* ------------------------------------------------------------------------- */
+void or_hermite_correct(int64_t n, const double *h, const double *x0, const double *v0,
+                        const double *a0, const double *j0, const double *a1,
+                        const double *j1, double *x1, double *v1, double *a2, double *a3)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double dt = h[i];
+        for (int k = 0; k < 3; ++k) {
+            int64_t q = (int64_t)k * n + i;
+            double vn = v0[q] + dt / 2 * (a0[q] + a1[q]) + dt * dt / 12 * (j0[q] - j1[q]);
+            double xn = x0[q] + dt / 2 * (v0[q] + vn) + dt * dt / 12 * (a0[q] - a1[q]);
+            double s0 = (-6 * (a0[q] - a1[q]) - dt * (4 * j0[q] + 2 * j1[q])) / (dt * dt);
+            double c = (12 * (a0[q] - a1[q]) + 6 * dt * (j0[q] + j1[q])) / (dt * dt * dt);
+            v1[q] = vn;
+            x1[q] = xn;
+            a2[q] = s0 + dt * c;
+            a3[q] = c;
+        }
+    }
+}
+
 int or_version(void) { return 1; }

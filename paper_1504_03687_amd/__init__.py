@@ -25,12 +25,14 @@ import torch
 __all__ = [
     "NbError", "Context", "lib", "library_path", "context", "predict", "regular_force",
     "regular_force_adjoint", "regular_force_batched", "autotune", "RegularForce",
+    "irregular_force", "hermite_correct", "potential",
     "FP64", "MIXED", "STATUS_OVERFLOW", "STATUS_BAD_INDEX", "STATUS_NONFINITE",
 ]
 
 FP64, MIXED = 0, 1
 STATUS_OVERFLOW, STATUS_BAD_INDEX, STATUS_NONFINITE = 1, 2, 4
-CLASS_FORCE, CLASS_MERGE, CLASS_PREDICT, CLASS_ADJOINT, CLASS_BATCHED, CLASS_REDO = range(6)
+(CLASS_FORCE, CLASS_MERGE, CLASS_PREDICT, CLASS_ADJOINT, CLASS_BATCHED, CLASS_REDO,
+ CLASS_STEP) = range(7)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # NBREG_LIBRARY may point at another build of the same library (e.g. a
@@ -87,6 +89,10 @@ def lib() -> C.CDLL:
             "nb_regular_force_batched": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, i32, C.c_int, vp,
                                           vp, vp, vp, vp, u32p], C.c_int),
             "nb_autotune": ([vp, i64, C.c_char_p, C.c_int], C.c_int),
+            "nb_irregular_force": ([vp, i64, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, u32p],
+                                   C.c_int),
+            "nb_hermite_correct": ([vp, i64] + [vp] * 11, C.c_int),
+            "nb_potential": ([vp, i64, vp, vp, vp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -344,6 +350,59 @@ def autotune(n: int, cache_path: str | None = None, force: bool = False,
     _check(lib().nb_autotune(ctx.handle, int(n),
                              cache_path.encode() if cache_path else None, int(bool(force))),
            "nb_autotune")
+
+
+def irregular_force(xp, vp, m, i_block, nb_cap, nb_count, nb_list, status=None,
+                    ctx: Context | None = None):
+    """Irregular acc, jerk (3, n_i) over the rows' neighbour lists (FP64)."""
+    n = m.shape[0]
+    n_i = i_block.shape[0]
+    _dev(xp, "xp", torch.float64, (3, n))
+    _dev(vp, "vp", torch.float64, (3, n))
+    _dev(m, "m", torch.float64, (n,))
+    _dev(i_block, "i_block", torch.int32, (n_i,))
+    _dev(nb_count, "nb_count", torch.int32, (n_i,))
+    _dev(nb_list, "nb_list", torch.int32, (n_i, nb_cap))
+    if status is not None:
+        _dev(status, "status", torch.int32, (1,))
+    acc = torch.empty((3, n_i), dtype=torch.float64, device=xp.device)
+    jerk = torch.empty_like(acc)
+    ctx = ctx or context(xp.device.index)
+    ctx._bind_stream()
+    _check(lib().nb_irregular_force(ctx.handle, n, _ptr(xp), _ptr(vp), _ptr(m), n_i,
+                                    _ptr(i_block), int(nb_cap), _ptr(nb_count),
+                                    _ptr(nb_list) if nb_cap > 0 else None, _ptr(acc),
+                                    _ptr(jerk), _ptr(status)), "nb_irregular_force")
+    return acc, jerk
+
+
+def hermite_correct(h, x0, v0, a0, j0, a1, j1, ctx: Context | None = None):
+    """Fourth-order Hermite corrector: returns (x1, v1, a2, a3), each (3, n)."""
+    n = h.shape[0]
+    _dev(h, "h", torch.float64, (n,))
+    for name, t in (("x0", x0), ("v0", v0), ("a0", a0), ("j0", j0), ("a1", a1), ("j1", j1)):
+        _dev(t, name, torch.float64, (3, n))
+    outs = [torch.empty_like(x0) for _ in range(4)]
+    ctx = ctx or context(x0.device.index)
+    ctx._bind_stream()
+    _check(lib().nb_hermite_correct(ctx.handle, n, _ptr(h), _ptr(x0), _ptr(v0), _ptr(a0),
+                                    _ptr(j0), _ptr(a1), _ptr(j1), *[_ptr(o) for o in outs]),
+           "nb_hermite_correct")
+    return tuple(outs)
+
+
+def potential(x, m, ctx: Context | None = None):
+    """(phi (n,), U (1,)): per-body potential and total potential energy (FP64)."""
+    n = m.shape[0]
+    _dev(x, "x", torch.float64, (3, n))
+    _dev(m, "m", torch.float64, (n,))
+    phi = torch.empty_like(m)
+    U = torch.empty(1, dtype=torch.float64, device=x.device)
+    ctx = ctx or context(x.device.index)
+    ctx._bind_stream()
+    _check(lib().nb_potential(ctx.handle, n, _ptr(x), _ptr(m), _ptr(phi), _ptr(U)),
+           "nb_potential")
+    return phi, U
 
 
 class RegularForce(torch.autograd.Function):

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <tuple>
@@ -18,7 +19,8 @@ enum {
     NB_CLASS_ADJOINT = 3,
     NB_CLASS_BATCHED = 4,
     NB_CLASS_REDO = 5,
-    NB_NCLASS = 6
+    NB_CLASS_STEP = 6,
+    NB_NCLASS = 7
 };
 
 namespace nbrt {

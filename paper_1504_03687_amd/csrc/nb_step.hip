@@ -1,0 +1,282 @@
+// The rest of an Ahmad-Cohen block step around the regular force (Wang et al.
+// 2015, section 2; Table 1 "Irr." and "Adjust"):
+//  * irregular force + jerk over each row's neighbour list (the bodies inside
+//    the neighbour radius, section 2), FP64, one wave per row with the list
+//    spread over the lanes (gathers from the SoA planes);
+//  * the fourth-order Hermite corrector of the integrator (section 2), FP64,
+//    one thread per entry, with the second and third force derivatives from
+//    the cubic Hermite interpolant (used by step-size criteria);
+//  * the O(N^2) potential (section 3.2.1 and the energy check / scaling of
+//    section 3.3.2), FP64, one body per lane with j-tiles in LDS, and a
+//    fixed-order reduction of the total potential energy.
+#include "nbreg.h"
+#include "nb_rows.h"
+#include "nb_runtime.h"
+
+namespace nb {
+namespace {
+
+__global__ __launch_bounds__(kBlock) void irregular_kernel(int64_t n, const double *xp,
+                                                           const double *vp, const double *m,
+                                                           int32_t n_i, const int32_t *i_block,
+                                                           int32_t cap, const int32_t *nb_count,
+                                                           const int32_t *nb_list, double *acc,
+                                                           double *jerk, uint32_t *status)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t b = (int64_t)blockIdx.x * (kBlock / kWave) +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (b >= n_i) return;
+    const int64_t i = i_block[b];
+    bool bad = i < 0 || i >= n;
+    double ax = 0, ay = 0, az = 0, jx = 0, jy = 0, jz = 0;
+    if (!bad) {
+        const double xi = xp[i], yi = xp[n + i], zi = xp[2 * n + i];
+        const double vxi = vp[i], vyi = vp[n + i], vzi = vp[2 * n + i];
+        const int32_t c = nb_count[b];
+        const int32_t k = c < cap ? c : cap;
+        for (int32_t q = lane; q < k; q += kWave) {
+            const int64_t j = nb_list[b * (int64_t)cap + q];
+            if (j < 0 || j >= n || j == i) {
+                bad = true;
+                continue;
+            }
+            add_term_f64(ax, ay, az, jx, jy, jz, xp[j] - xi, xp[n + j] - yi, xp[2 * n + j] - zi,
+                         vp[j] - vxi, vp[n + j] - vyi, vp[2 * n + j] - vzi, m[j]);
+        }
+    }
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    az = wave_sum(az);
+    jx = wave_sum(jx);
+    jy = wave_sum(jy);
+    jz = wave_sum(jz);
+    const bool nonfin = !finite6(ax, ay, az, jx, jy, jz);
+    const uint64_t bb = __ballot(bad);
+    if (lane == 0) {
+        acc[b] = ax;
+        acc[n_i + b] = ay;
+        acc[2 * (int64_t)n_i + b] = az;
+        jerk[b] = jx;
+        jerk[n_i + b] = jy;
+        jerk[2 * (int64_t)n_i + b] = jz;
+        if (status && (bb || nonfin))
+            atomicOr(status, (bb ? kStBadIndex : 0u) | (nonfin ? kStNonFinite : 0u));
+    }
+}
+
+// Fourth-order Hermite corrector, the textbook two-point form, evaluated in
+// the same operation order as its plain definition:
+//   v1 = v0 + h/2 (a0 + a1) + h^2/12 (j0 - j1)
+//   x1 = x0 + h/2 (v0 + v1) + h^2/12 (a0 - a1)
+//   a3 = (12 (a0 - a1) + 6 h (j0 + j1)) / h^3
+//   a2 = (-6 (a0 - a1) - h (4 j0 + 2 j1)) / h^2 + h a3     (at the step end)
+__global__ __launch_bounds__(256) void corrector_kernel(int64_t n, const double *h,
+                                                       const double *x0, const double *v0,
+                                                       const double *a0, const double *j0,
+                                                       const double *a1, const double *j1,
+                                                       double *x1, double *v1, double *a2,
+                                                       double *a3)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double dt = h[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t q = (int64_t)k * n + i;
+            const double A0 = a0[q], A1 = a1[q], J0 = j0[q], J1 = j1[q], V0 = v0[q];
+            const double vn = V0 + dt / 2 * (A0 + A1) + dt * dt / 12 * (J0 - J1);
+            const double xn = x0[q] + dt / 2 * (V0 + vn) + dt * dt / 12 * (A0 - A1);
+            const double s0 = (-6 * (A0 - A1) - dt * (4 * J0 + 2 * J1)) / (dt * dt);
+            const double c = (12 * (A0 - A1) + 6 * dt * (J0 + J1)) / (dt * dt * dt);
+            v1[q] = vn;
+            x1[q] = xn;
+            a2[q] = s0 + dt * c;
+            a3[q] = c;
+        }
+    }
+}
+
+struct alignas(16) PBody {
+    double x, y, z, m;
+};
+
+// phi_i = -sum_{j != i} m_j / |x_j - x_i|.  grid = (ceil(n / kBlock), splits);
+// split s writes partial phi to part[s][n] (or phi directly when splits == 1).
+__global__ __launch_bounds__(kBlock) void potential_kernel(int64_t n, const double *x,
+                                                           const double *m, int32_t splits,
+                                                           int64_t split_len, double *out)
+{
+    __shared__ PBody tile[2][kTile];
+    const int tid = threadIdx.x;
+    const int32_t split = blockIdx.y;
+    const int64_t j0 = (int64_t)split * split_len;
+    const int64_t j1 = j0 + split_len < n ? j0 + split_len : n;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + tid;
+    double xi = kFar * 0.5, yi = kFar * 0.5, zi = kFar * 0.5;
+    if (i < n) {
+        xi = x[i];
+        yi = x[n + i];
+        zi = x[2 * n + i];
+    }
+    double phi = 0.0;
+    const int64_t ntiles = j1 > j0 ? (j1 - j0 + kTile - 1) / kTile : 0;
+    PBody nxt;
+    auto load = [&](int64_t j) {
+        if (j < j1) {
+            nxt.x = x[j];
+            nxt.y = x[n + j];
+            nxt.z = x[2 * n + j];
+            nxt.m = m[j];
+        } else {
+            nxt.x = nxt.y = nxt.z = kFar;
+            nxt.m = 0.0;
+        }
+    };
+    if (ntiles > 0) {
+        load(j0 + tid);
+        tile[0][tid] = nxt;
+    }
+    __syncthreads();
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int cur = (int)(t & 1);
+        const int64_t tbase = j0 + t * kTile;
+        if (t + 1 < ntiles) load(tbase + kTile + tid);
+        const PBody *buf = tile[cur];
+#pragma unroll 4
+        for (int jj = 0; jj < kTile; ++jj) {
+            const PBody &J = buf[jj];
+            const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            double y = rsqrt_f64(r2);
+            y = (tbase + jj == i) ? 0.0 : y;
+            phi = __builtin_fma(-J.m, y, phi);
+        }
+        if (t + 1 < ntiles) tile[cur ^ 1][tid] = nxt;
+        __syncthreads();
+    }
+    if (i < n) out[(int64_t)split * n + i] = phi;
+}
+
+// Sums split partials (fixed order) into phi and forms m_i phi_i / 2 per
+// body; then a fixed-shape tree reduction of those into one value per
+// work-group, and a final single-work-group pass.
+__global__ __launch_bounds__(256) void potential_reduce(int64_t n, const double *m,
+                                                        int32_t splits, const double *part,
+                                                        double *phi, double *wg_sum)
+{
+    __shared__ double red[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double e = 0.0;
+    if (i < n) {
+        double p = 0.0;
+        for (int32_t s = 0; s < splits; ++s) p += part[(int64_t)s * n + i];
+        phi[i] = p;
+        e = 0.5 * m[i] * p;
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) wg_sum[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void sum_kernel(int64_t count, const double *v, double *out)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < count; k += 256) s += v[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+}  // namespace
+}  // namespace nb
+
+using namespace nbrt;
+
+extern "C" {
+
+int nb_irregular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                       const double *m, int32_t n_i, const int32_t *i_block, int32_t nb_cap,
+                       const int32_t *nb_count, const int32_t *nb_list, double *acc,
+                       double *jerk, uint32_t *status)
+{
+    if (!ctx || n <= 0 || n > INT32_MAX || n_i < 0 || nb_cap < 0) return NB_ERR_INVALID_ARG;
+    if (!xp || !vp || !m) return NB_ERR_INVALID_ARG;
+    if (n_i > 0 && (!i_block || !nb_count || !acc || !jerk)) return NB_ERR_INVALID_ARG;
+    if (n_i > 0 && nb_cap > 0 && !nb_list) return NB_ERR_INVALID_ARG;
+    if (!ctx->usable) return NB_ERR_UNSUPPORTED;
+    if (n_i == 0) return NB_OK;
+    const int per = nb::kBlock / nb::kWave;
+    hipEvent_t ev[2];
+    hipError_t e = timed_begin(ctx, NB_CLASS_STEP, ev);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(nb::irregular_kernel, dim3((unsigned)((n_i + per - 1) / per)),
+                           dim3(nb::kBlock), 0, ctx->stream, n, xp, vp, m, n_i, i_block, nb_cap,
+                           nb_count, nb_list, acc, jerk, status);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_STEP, ev);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
+}
+
+int nb_hermite_correct(nb_ctx *ctx, int64_t n, const double *h, const double *x0,
+                       const double *v0, const double *a0, const double *j0, const double *a1,
+                       const double *j1, double *x1, double *v1, double *a2, double *a3)
+{
+    if (!ctx || n <= 0 || n > INT32_MAX) return NB_ERR_INVALID_ARG;
+    if (!h || !x0 || !v0 || !a0 || !j0 || !a1 || !j1 || !x1 || !v1 || !a2 || !a3)
+        return NB_ERR_INVALID_ARG;
+    if (!ctx->usable) return NB_ERR_UNSUPPORTED;
+    const int64_t want = (n + 255) / 256;
+    const unsigned grid = (unsigned)(want < 65536 ? want : 65536);
+    hipLaunchKernelGGL(nb::corrector_kernel, dim3(grid), dim3(256), 0, ctx->stream, n, h, x0, v0,
+                       a0, j0, a1, j1, x1, v1, a2, a3);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
+}
+
+int nb_potential(nb_ctx *ctx, int64_t n, const double *x, const double *m, double *phi,
+                 double *energy)
+{
+    if (!ctx || n <= 0 || n > INT32_MAX || !x || !m || !phi) return NB_ERR_INVALID_ARG;
+    if (!ctx->usable) return NB_ERR_UNSUPPORTED;
+    const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
+    const int64_t wgs = (n + nb::kBlock - 1) / nb::kBlock;
+    int64_t splits = std::max<int64_t>(1, std::min<int64_t>((cus * 8 + wgs - 1) / wgs,
+                                                             std::max<int64_t>(1, n / 1024)));
+    const int64_t tiles = (n + nb::kTile - 1) / nb::kTile;
+    const int64_t split_len = (tiles + splits - 1) / splits * nb::kTile;
+    splits = (n + split_len - 1) / split_len;
+    const int64_t red_wgs = (n + 255) / 256;
+    const size_t bytes = (size_t)(splits * n + red_wgs + 1) * sizeof(double) + 512;
+    int rc = ensure_scratch(ctx, bytes);
+    if (rc != NB_OK) return rc;
+    double *part = (double *)ctx->scratch;
+    double *wg = part + splits * n;
+    double *tot = wg + red_wgs;
+    hipEvent_t ev[2];
+    hipError_t e = timed_begin(ctx, NB_CLASS_STEP, ev);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(nb::potential_kernel, dim3((unsigned)wgs, (unsigned)splits),
+                           dim3(nb::kBlock), 0, ctx->stream, n, x, m, (int32_t)splits, split_len,
+                           part);
+        hipLaunchKernelGGL(nb::potential_reduce, dim3((unsigned)red_wgs), dim3(256), 0,
+                           ctx->stream, n, m, (int32_t)splits, part, phi, wg);
+        hipLaunchKernelGGL(nb::sum_kernel, dim3(1), dim3(256), 0, ctx->stream, red_wgs, wg,
+                           energy ? energy : tot);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_STEP, ev);
+    return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
+}
+
+}  // extern "C"

@@ -334,3 +334,53 @@ def test_adjoint_is_linear_in_weights_and_matches_forward():
     wa[:] = 0; wj[2, 11] = 1.0
     gx, gv, gm = oracle.adjoint(x, v, m, blk, s["rs2"], wa, wj)
     assert abs((gm * m).sum() - jerk[2, 11]) <= 1e-13 * np.abs(jerk[:, 11]).sum()
+
+
+# --------------------------------------------------------------------------- #
+# Hermite corrector
+# --------------------------------------------------------------------------- #
+def test_hermite_corrector_exact_for_cubic_force():
+    """For a force history that is a cubic polynomial in time the corrector's
+    velocity update (two-point Hermite quadrature) and the interpolated a2, a3
+    are exact; the position update is exact when, in addition, a is at most
+    quadratic (the velocity is then cubic)."""
+    rng = np.random.default_rng(21)
+    n = 50
+    h = np.ldexp(1.0, -rng.integers(2, 8, n))
+    x0, v0, A0, J0, S0 = (rng.standard_normal((3, n)) for _ in range(5))
+    C0 = rng.standard_normal((3, n))
+    for cubic in (C0, np.zeros((3, n))):
+        a = lambda t: A0 + J0 * t + S0 * t ** 2 / 2 + cubic * t ** 3 / 6
+        jd = lambda t: J0 + S0 * t + cubic * t ** 2 / 2
+        vx = lambda t: v0 + A0 * t + J0 * t ** 2 / 2 + S0 * t ** 3 / 6 + cubic * t ** 4 / 24
+        xx = lambda t: (x0 + v0 * t + A0 * t ** 2 / 2 + J0 * t ** 3 / 6 + S0 * t ** 4 / 24
+                        + cubic * t ** 5 / 120)
+        x1, v1, a2, a3 = oracle.hermite_correct(h, x0, v0, a(0), jd(0), a(h), jd(h))
+        assert np.allclose(v1, vx(h), rtol=0, atol=1e-13)
+        # a2, a3 divide differences of O(1) forces by h^2, h^3: allow that rounding
+        assert np.all(np.abs(a3 - cubic) <= 64 * 2.0 ** -52 * 4 / h ** 3)
+        assert np.all(np.abs(a2 - (S0 + cubic * h)) <= 64 * 2.0 ** -52 * 4 / h ** 2)
+        if not cubic.any():
+            assert np.allclose(x1, xx(h), rtol=0, atol=1e-13)
+
+
+def test_hermite_two_body_orbit_fourth_order():
+    """Integrate a circular two-body orbit for one period with predictor ->
+    full force (rs2 = 0) -> corrector; the position error after one period
+    falls by ~2^4 when the step halves."""
+    def run(steps):
+        m = np.array([0.5, 0.5])
+        x = np.array([[0.5, -0.5], [0.0, 0.0], [0.0, 0.0]])
+        v = np.array([[0.0, 0.0], [0.5, -0.5], [0.0, 0.0]])   # circular: v^2 = M/(4 r)
+        blk = np.array([0, 1], np.int32)
+        a, j, *_ = oracle.regular(x, v, m, blk, np.zeros(2), 2)
+        period = 2 * np.pi * np.sqrt(1.0 / 1.0)            # a_rel = 1, M = 1
+        h = period / steps
+        for k in range(steps):
+            xp, vp = oracle.predict(h, x, v, a, j, np.zeros(2))
+            a1, j1, *_ = oracle.regular(xp, vp, m, blk, np.zeros(2), 2)
+            x, v, _, _ = oracle.hermite_correct(np.full(2, h), x, v, a, j, a1, j1)
+            a, j = a1, j1
+        return np.abs(x - np.array([[0.5, -0.5], [0, 0], [0, 0]])).max()
+    e1, e2 = run(200), run(400)
+    assert e1 < 1e-5 and 12 < e1 / e2 < 20, (e1, e2)
