@@ -44,6 +44,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("nb_internal.h", "nb_pair.h", "nb_rows.h", "nb_force.hip")
+
+
+def kernel_src_hash() -> str:
+    """SHA-1 over the sources of the regular-force kernels."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1504_03687_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(prec: str):
+    """HBM bytes per launch of the full-block force kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that summary was
+    taken on different kernel sources (or does not exist)."""
+    path = os.path.join(ROOT, "profiles", "force_rows_kernel_full_block_n1048576.traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_src_sha1") != kernel_src_hash():
+        return None
+    return d.get(prec, {}).get("hbm_bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +199,72 @@ def main():
         levels["aggregate_gpairs_per_s"] = {
             p: round(tot_pairs[p] / tot_time[p] * 1e-6, 2) for p in precs}
 
+    # small blocks (HBM / latency bound): random rows of the same cluster
+    small = {}
+    if not args.no_levels:
+        rng = np.random.default_rng(1)
+        for size in (1, 32, 1024):
+            sb = rng.choice(n, size, replace=False).astype(np.int32)
+            bd, rd = dev(sb), dev(s["rs2"][sb])
+            ent = {}
+            for prec in precs:
+                nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
+                torch.cuda.synchronize()
+                reps = 20
+                c1 = time.perf_counter()
+                for _ in range(reps):
+                    nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
+                torch.cuda.synchronize()
+                us = (time.perf_counter() - c1) * 1e6 / reps
+                ent[prec] = {"us": round(us, 1),
+                             "gpairs_per_s": round(size * (n - 1) / us * 1e-3, 2),
+                             "jset_GB_per_s": round(56.0 * n / us * 1e-3, 1),
+                             "plan": ctx.last_plan()}
+            small[str(size)] = ent
+            log(f"small block n_i={size}: " + " ".join(
+                f"{pp}={ent[pp]['us']} us" for pp in precs))
+
+    # adjoint (N = 65536 all active, FP64) and the batched ensemble
+    # (256 clusters, one graph launch), each timed over a few calls
+    extras = {}
+    if not args.no_levels:
+        s5 = W.config5()
+        n5 = s5["n"]
+        a5 = [dev(s5[k]) for k in ("x", "v", "m", "i_block", "rs2", "w_a", "w_j")]
+        nb.regular_force_adjoint(*a5, ctx=ctx)
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        for _ in range(3):
+            nb.regular_force_adjoint(*a5, ctx=ctx)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - c1) * 1e3 / 3
+        extras["adjoint"] = {"workload": f"N={n5} Plummer+Kroupa, all active, FP64",
+                             "ms": round(ms, 3),
+                             "gpairs_per_s_per_pass": round(n5 * (n5 - 1) / ms * 1e-6, 2)}
+        log(f"adjoint: {ms:.2f} ms")
+        s4 = W.config4()
+        xp4, vp4, _ = nb.predict(dev(s4["x"]), dev(s4["v"]), dev(s4["a"]), dev(s4["jk"]),
+                                 dev(s4["t0"]), s4["t"], ctx=ctx)
+        b4 = (s4["j_off"], s4["i_off"], xp4, vp4, dev(s4["m"]), dev(s4["i_block"]),
+              dev(s4["rs2"]))
+        sizes = np.diff(s4["j_off"])
+        rows = np.diff(s4["i_off"])
+        pairs4 = float((sizes * rows).sum())
+        for prec in precs:
+            o4 = nb.regular_force_batched(*b4, s4["nb_cap"], prec, ctx=ctx)
+            torch.cuda.synchronize()
+            c1 = time.perf_counter()
+            for _ in range(5):
+                nb.regular_force_batched(*b4, s4["nb_cap"], prec, out=o4, ctx=ctx)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - c1) * 1e3 / 5
+            extras[f"batched_{prec}"] = {
+                "workload": "256 clusters, N log-uniform [1024, 32768], active 1-100%",
+                "ms": round(ms, 3), "gpairs_per_s": round(pairs4 / ms * 1e-6, 2),
+                "plan": ctx.last_plan()}
+            log(f"batched {prec}: {ms:.2f} ms, {pairs4 / ms * 1e-6:.1f} G pairs/s")
+            del o4
+
     # CPU oracle on a bounded sample of the same full block
     cpu = None
     if args.cpu_rows > 0:
@@ -211,7 +305,8 @@ def main():
                                "block (all bodies active), predict + regular force, nb_cap 1024",
                    "n": n, "n_i": n_i, "pairs_per_step": pairs},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": measured_traffic(dom),
                      "kernel": f"force_rows_kernel ({dom})",
                      "flops_per_pair": FLOPS_PER_PAIR,
                      "frac_of_unpacked_fp32_fp64_peak": round(achieved / PEAK_UNPACKED, 4)},
@@ -226,6 +321,8 @@ def main():
                            "plan": r["plan"], "overflow": r["overflow"]}
                        for p, r in res.items()},
         "levels": levels,
+        "small_blocks": small or None,
+        "extras": extras or None,
     }
     if "mixed" in res and "fp64" in res:
         line["mixed_over_fp64"] = round(res["mixed"]["pairs_per_s"] / res["fp64"]["pairs_per_s"], 3)
