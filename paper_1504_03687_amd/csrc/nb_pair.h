@@ -56,23 +56,29 @@ struct Sums<false> {
 // varying sign this estimates sum |term|^2, the scale of the accumulated FP32
 // rounding error of the row (which grows like its square root); rows whose
 // estimated relative error is too large are recomputed in FP64.
+// The jerk partial is kept as two parts, sum m r^-3 u and sum m r^-3 (r.u)
+// r^-2 r, combined as (first - 3 * second) at the fold, so the factor -3 is
+// applied once per run instead of once per pair.
 template <>
 struct Sums<true> {
     double ax, ay, az, jx, jy, jz;
     double va, vj;
-    float pax, pay, paz, pjx, pjy, pjz;
+    float pax, pay, paz, pjx, pjy, pjz, prx, pry, prz;
     __device__ __forceinline__ void zero()
     {
         ax = ay = az = jx = jy = jz = va = vj = 0.0;
-        pax = pay = paz = pjx = pjy = pjz = 0.0f;
+        pax = pay = paz = pjx = pjy = pjz = prx = pry = prz = 0.0f;
     }
     __device__ __forceinline__ void fold()
     {
+        const float qx = __builtin_fmaf(-3.0f, prx, pjx);
+        const float qy = __builtin_fmaf(-3.0f, pry, pjy);
+        const float qz = __builtin_fmaf(-3.0f, prz, pjz);
         ax += (double)pax; ay += (double)pay; az += (double)paz;
-        jx += (double)pjx; jy += (double)pjy; jz += (double)pjz;
+        jx += (double)qx; jy += (double)qy; jz += (double)qz;
         va += (double)__builtin_fmaf(paz, paz, __builtin_fmaf(pay, pay, pax * pax));
-        vj += (double)__builtin_fmaf(pjz, pjz, __builtin_fmaf(pjy, pjy, pjx * pjx));
-        pax = pay = paz = pjx = pjy = pjz = 0.0f;
+        vj += (double)__builtin_fmaf(qz, qz, __builtin_fmaf(qy, qy, qx * qx));
+        pax = pay = paz = pjx = pjy = pjz = prx = pry = prz = 0.0f;
     }
 };
 
@@ -117,13 +123,16 @@ __device__ __forceinline__ void accum_mixed(Sums<true> &S, float fx, float fy, f
     const float y2 = y * y;
     const float mr3 = (mj * y) * y2;
     const float s = __builtin_fmaf(fz, gz, __builtin_fmaf(fy, gy, fx * gx));
-    const float q = (s * y2) * (-3.0f * mr3);
+    const float q = (s * y2) * mr3;                 // m (r.u) / r^5; -3 applied at the fold
     S.pax = __builtin_fmaf(mr3, fx, S.pax);
     S.pay = __builtin_fmaf(mr3, fy, S.pay);
     S.paz = __builtin_fmaf(mr3, fz, S.paz);
-    S.pjx = __builtin_fmaf(q, fx, __builtin_fmaf(mr3, gx, S.pjx));
-    S.pjy = __builtin_fmaf(q, fy, __builtin_fmaf(mr3, gy, S.pjy));
-    S.pjz = __builtin_fmaf(q, fz, __builtin_fmaf(mr3, gz, S.pjz));
+    S.pjx = __builtin_fmaf(mr3, gx, S.pjx);
+    S.pjy = __builtin_fmaf(mr3, gy, S.pjy);
+    S.pjz = __builtin_fmaf(mr3, gz, S.pjz);
+    S.prx = __builtin_fmaf(q, fx, S.prx);
+    S.pry = __builtin_fmaf(q, fy, S.pry);
+    S.prz = __builtin_fmaf(q, fz, S.prz);
 }
 
 // FP64 regular term added straight into FP64 running sums (used by the mixed
