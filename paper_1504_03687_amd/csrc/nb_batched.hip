@@ -217,7 +217,8 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     const size_t b_it = r256(std::max<size_t>(1, it_dev.size()) * sizeof(nb::BItem));
     const size_t b_mr = r256(std::max<size_t>(1, merge_rows.size()) * sizeof(int32_t));
     const size_t b_slots = nb::slot_scratch_bytes(slots);
-    const size_t b_redo = c->redo_k > 0.0 ? nb::redo_scratch_bytes(f.n_i) : 0;
+    const int32_t groups = nb::redo_groups_for(ctx->cu_count);
+    const size_t b_redo = c->redo_k > 0.0 ? nb::redo_scratch_bytes(f.n_i, groups) : 0;
     const size_t total = b_queue + b_cl + 2 * b_mr + b_it + b_slots + b_redo;
     if (ctx->scratch_limit && total > ctx->scratch_limit) return NB_ERR_OOM;
     hipError_t e = hipMalloc(&c->dmem, total);
@@ -258,7 +259,7 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     A.f = f;
     nb::bind_slot_scratch(A.f, slots, dslots);
     A.f.redo_k = c->redo_k;
-    if (c->redo_k > 0.0) nb::bind_redo_scratch(A.f, dredo);
+    if (c->redo_k > 0.0) nb::bind_redo_scratch(A.f, dredo, groups);
     A.f.splits = 0;          // per-cluster
     A.f.split_len = 0;
     A.clusters = dcl;
@@ -285,7 +286,7 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
         if (le == hipSuccess) le = nb::launch_batched(mixed, c->rows_per_lane, c->grid, A, cs);
         if (le == hipSuccess) le = nb::launch_batched_merge(A, cs);
         if (le == hipSuccess && c->redo_k > 0.0)
-            le = nb::launch_redo(A.f, ctx->cu_count, cs);
+            le = nb::launch_redo(A.f, cs);
         e = hipStreamEndCapture(cs, &c->graph);
         if (e == hipSuccess) e = le;
     }

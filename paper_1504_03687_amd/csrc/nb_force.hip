@@ -102,10 +102,12 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
     }
 
     int iter = 0;
+    JBody Jn;
+    load_body(Jn, a, j0 + lane, j1);
     for (int64_t base = j0; base < j1; base += kWave) {
         const int64_t j = base + lane;
-        JBody J;
-        load_body(J, a, j, j1);
+        const JBody J = Jn;
+        if (base + kWave < j1) load_body(Jn, a, j + kWave, j1);   // prefetch
         const int32_t jidx = (int32_t)j;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -191,14 +193,46 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(ForceArgs a)
     merge_row(a, b, g);
 }
 
-// Persistent waves over the redo list.
-__global__ __launch_bounds__(kBlock) void redo_kernel(ForceArgs a)
+// One work-group per row for plans with many splits.
+__global__ __launch_bounds__(kBlock) void merge_wg_kernel(ForceArgs a)
 {
-    const int32_t gw = (int32_t)(blockIdx.x * (kBlock / kWave)) +
-                       __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int32_t nw = (int32_t)(gridDim.x * (kBlock / kWave));
+    __shared__ double lds[kBlock / kWave];
+    __shared__ int64_t scan[kBlock];
+    const int64_t b = blockIdx.x;
+    const MergeGeom g{a.splits, b, a.n_i, 0, a.n, a.split_len};
+    merge_row_wg(a, b, g, lds, scan);
+}
+
+// Refinement, pass 1: (row, chunk) items over a fixed grid of work-groups.
+__global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
+{
+    __shared__ double lds[kBlock / kWave];
     const int32_t count = __builtin_amdgcn_readfirstlane(*(volatile int32_t *)a.redo_count);
-    for (int32_t q = gw; q < count; q += nw) redo_row(a, q);
+    const int32_t cpr = redo_chunks(count, a.redo_groups);
+    const int64_t items = (int64_t)count * cpr;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x)
+        redo_chunk(a, (int32_t)(it / cpr), (int32_t)(it % cpr), cpr, lds);
+}
+
+// Refinement, pass 2: sum each row's chunks in order and overwrite its forces.
+__global__ __launch_bounds__(256) void redo_final_kernel(ForceArgs a)
+{
+    const int32_t count = *(volatile int32_t *)a.redo_count;
+    const int32_t cpr = redo_chunks(count, a.redo_groups);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        for (int32_t c = 0; c < cpr; ++c)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) v[k] += a.redo_part[(q * cpr + c) * 6 + k];
+        const int64_t b = a.redo_rows[q];
+        a.acc[b] = v[0];
+        a.acc[a.n_i + b] = v[1];
+        a.acc[2 * (int64_t)a.n_i + b] = v[2];
+        a.jerk[b] = v[3];
+        a.jerk[a.n_i + b] = v[4];
+        a.jerk[2 * (int64_t)a.n_i + b] = v[5];
+    }
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int32_t value, int64_t count)
@@ -219,12 +253,17 @@ size_t slot_scratch_bytes(int64_t slots)
            round256(s * kSegCap * sizeof(int32_t));
 }
 
-size_t redo_scratch_bytes(int32_t n_i)
+int32_t redo_groups_for(int cu_count) { return (cu_count > 0 ? cu_count : 256) * 4; }
+
+size_t redo_scratch_bytes(int32_t n_i, int32_t groups)
 {
-    return 256 + 3 * round256((size_t)(n_i > 0 ? n_i : 1) * sizeof(int32_t));
+    const int64_t rows = n_i > 0 ? n_i : 1;
+    const int64_t parts = rows > groups ? rows : groups;
+    return 256 + 3 * round256((size_t)rows * sizeof(int32_t)) +
+           round256((size_t)parts * 6 * sizeof(double));
 }
 
-void bind_redo_scratch(ForceArgs &a, void *base)
+void bind_redo_scratch(ForceArgs &a, void *base, int32_t groups)
 {
     char *p = (char *)base;
     const size_t arr = round256((size_t)(a.n_i > 0 ? a.n_i : 1) * sizeof(int32_t));
@@ -232,14 +271,15 @@ void bind_redo_scratch(ForceArgs &a, void *base)
     a.redo_rows = (int32_t *)(p + 256);
     a.redo_j0 = (int32_t *)(p + 256 + arr);
     a.redo_j1 = (int32_t *)(p + 256 + 2 * arr);
+    a.redo_part = (double *)(p + 256 + 3 * arr);
+    a.redo_groups = groups;
 }
 
-hipError_t launch_redo(const ForceArgs &a, int cu_count, hipStream_t s)
+hipError_t launch_redo(const ForceArgs &a, hipStream_t s)
 {
-    const int64_t waves = std::min<int64_t>((int64_t)(cu_count > 0 ? cu_count : 256) * 16,
-                                            (a.n_i + 0) > 0 ? a.n_i : 1);
-    const int64_t per = kBlock / kWave;
-    hipLaunchKernelGGL(redo_kernel, dim3((unsigned)((waves + per - 1) / per)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(redo_part_kernel, dim3((unsigned)a.redo_groups), dim3(kBlock), 0, s, a);
+    const int64_t rows = a.n_i > 0 ? a.n_i : 1;
+    hipLaunchKernelGGL(redo_final_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s,
                        a);
     return hipGetLastError();
 }
@@ -307,9 +347,13 @@ hipError_t launch_force(const Plan &p, bool mixed, const ForceArgs &a, hipStream
 hipError_t launch_merge(bool mixed, const ForceArgs &a, hipStream_t s)
 {
     (void)mixed;
-    const int per = kBlock / kWave;
-    dim3 grid((unsigned)((a.n_i + per - 1) / per));
-    hipLaunchKernelGGL(merge_kernel, grid, dim3(kBlock), 0, s, a);
+    if (a.splits >= 256) {   // few rows, many splits: one work-group per row
+        hipLaunchKernelGGL(merge_wg_kernel, dim3((unsigned)a.n_i), dim3(kBlock), 0, s, a);
+    } else {
+        const int per = kBlock / kWave;
+        dim3 grid((unsigned)((a.n_i + per - 1) / per));
+        hipLaunchKernelGGL(merge_kernel, grid, dim3(kBlock), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -59,14 +59,18 @@ struct ForceArgs {
     int32_t *redo_count;  // device counter, zeroed before the force kernel
     int32_t *redo_rows;   // [n_i]
     int32_t *redo_j0, *redo_j1;
+    int32_t redo_groups;  // work-groups of the refinement kernel
+    double *redo_part;    // [max(redo_groups, n_i)][6] chunk partials
 };
 
 // Components per slot: acc x,y,z, jerk x,y,z, and the two error-scale sums.
 constexpr int kSlotComp = 8;
-// Extra scratch for the redo list of n_i rows (counter + 3 int arrays).
-size_t redo_scratch_bytes(int32_t n_i);
-void bind_redo_scratch(ForceArgs &a, void *base);
-hipError_t launch_redo(const ForceArgs &a, int cu_count, hipStream_t s);
+// Extra scratch for the redo list of n_i rows (counter, row / j-range arrays
+// and the chunk partials of 'groups' refinement work-groups).
+int32_t redo_groups_for(int cu_count);
+size_t redo_scratch_bytes(int32_t n_i, int32_t groups);
+void bind_redo_scratch(ForceArgs &a, void *base, int32_t groups);
+hipError_t launch_redo(const ForceArgs &a, hipStream_t s);
 
 struct Plan {
     int mapping;        // 1 = row per lane (LDS j-tiles), 2 = row group per wave

@@ -383,13 +383,38 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
     flush_flags(a, ovf, bad && lane == 0, nonfin);
 }
 
-// FP64 recompute of one listed row by one whole wave (j spread over lanes):
-// forces only; the neighbour list and count of the row are already final.
-__device__ __forceinline__ void redo_row(const ForceArgs &a, int32_t q)
+// Fixed-order sum of one value over the 256 lanes of a work-group (all
+// lanes must call it); every lane gets the result.
+__device__ __forceinline__ double block_sum(double v, double *lds /* [kBlock / kWave] */)
 {
-    const int lane = threadIdx.x & (kWave - 1);
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBlock / kWave; ++k) t += lds[k];
+    return t;
+}
+
+// Refinement: chunks per listed row so that 'groups' work-groups are busy.
+__device__ __forceinline__ int32_t redo_chunks(int32_t count, int32_t groups)
+{
+    const int32_t c = count > 0 ? groups / count : 1;
+    return c < 1 ? 1 : (c > 256 ? 256 : c);
+}
+
+// FP64 sums of one chunk of one listed row by a whole work-group (forces only;
+// the row's neighbour list and count are already final).
+__device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_t c,
+                                          int32_t cpr, double *lds)
+{
     const int64_t b = a.redo_rows[q];
     const int64_t j0 = a.redo_j0[q], j1 = a.redo_j1[q];
+    const int64_t clen = ((j1 - j0 + cpr - 1) / cpr + kWave - 1) / kWave * kWave;
+    const int64_t cj0 = j0 + (int64_t)c * clen;
+    const int64_t cj1 = cj0 + clen < j1 ? cj0 + clen : j1;
     const int64_t i = a.i_block[b];
     const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
     const double vxi = a.vp[i], vyi = a.vp[a.n + i], vzi = a.vp[2 * a.n + i];
@@ -397,10 +422,9 @@ __device__ __forceinline__ void redo_row(const ForceArgs &a, int32_t q)
     const double hi = cand_bound_f64(rs2f);
     Sums<false> S;
     S.zero();
-    for (int64_t base = j0; base < j1; base += kWave) {
-        const int64_t j = base + lane;
+    for (int64_t j = cj0 + threadIdx.x; j < cj1; j += kBlock) {
         JBody J;
-        load_body(J, a, j, j1);
+        load_body(J, a, j, cj1);
         const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         bool excl = false;
@@ -411,20 +435,103 @@ __device__ __forceinline__ void redo_row(const ForceArgs &a, int32_t q)
         }
         accum_f64(S, dx, dy, dz, r2, J.vx - vxi, J.vy - vyi, J.vz - vzi, J.m, excl);
     }
-    S.ax = wave_sum(S.ax);
-    S.ay = wave_sum(S.ay);
-    S.az = wave_sum(S.az);
-    S.jx = wave_sum(S.jx);
-    S.jy = wave_sum(S.jy);
-    S.jz = wave_sum(S.jz);
-    if (lane == 0) {
-        a.acc[b] = S.ax;
-        a.acc[a.n_i + b] = S.ay;
-        a.acc[2 * (int64_t)a.n_i + b] = S.az;
-        a.jerk[b] = S.jx;
-        a.jerk[a.n_i + b] = S.jy;
-        a.jerk[2 * (int64_t)a.n_i + b] = S.jz;
+    const double v[6] = {S.ax, S.ay, S.az, S.jx, S.jy, S.jz};
+    double *out = a.redo_part + ((int64_t)q * cpr + c) * 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double t = block_sum(v[k], lds);
+        if (threadIdx.x == 0) out[k] = t;
     }
+}
+
+// Merge of one row by a whole work-group, for plans with many splits: lane t
+// owns the contiguous splits [t*K, (t+1)*K), so summation order and list order
+// are fixed; a work-group prefix scan of the lanes' counts places the
+// segments.
+__device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, const MergeGeom &g,
+                                             double *lds, int64_t *scan)
+{
+    const int tid = threadIdx.x;
+    const int64_t i = a.i_block[b];
+    const bool bad = i < 0 || i >= a.n;
+    const int32_t S = g.splits;
+    const int64_t T = a.total_slots;
+    const int32_t K = (S + kBlock - 1) / kBlock;
+    const int32_t s0 = tid * K;
+    const int32_t s1 = s0 + K < S ? s0 + K : S;
+
+    double v[kSlotComp] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t mine = 0;
+    for (int32_t s = s0; s < s1; ++s) {
+        const int64_t slot = g.slot0 + (int64_t)s * g.slot_step;
+#pragma unroll
+        for (int k = 0; k < kSlotComp; ++k) v[k] += a.part[(int64_t)k * T + slot];
+        mine += a.seg_cnt[slot];
+    }
+#pragma unroll
+    for (int k = 0; k < kSlotComp; ++k) v[k] = block_sum(v[k], lds);
+
+    // exclusive scan of the lanes' neighbour counts (Hillis-Steele in LDS)
+    __syncthreads();
+    scan[tid] = mine;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const int64_t add = tid >= o ? scan[tid - o] : 0;
+        __syncthreads();
+        scan[tid] += add;
+        __syncthreads();
+    }
+    const int64_t total = scan[kBlock - 1];
+    int64_t start = scan[tid] - mine;
+
+    bool ovf = false, nonfin = false;
+    if (!bad) {
+        const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
+        const float rs2f = (float)a.rs2[b];
+        for (int32_t s = s0; s < s1 && start < a.cap; ++s) {
+            const int64_t slot = g.slot0 + (int64_t)s * g.slot_step;
+            const int32_t c = a.seg_cnt[slot];
+            if (c <= 0) continue;
+            const int64_t take = (int64_t)c < a.cap - start ? c : a.cap - start;
+            int32_t *dst = a.nb_list + b * (int64_t)a.cap + start;
+            if (c <= kSegCap) {
+                const int32_t *src = a.seg_list + slot * kSegCap;
+                for (int64_t q = 0; q < take; ++q) dst[q] = src[q];
+            } else {   // overflowed segment: rescan its j-range, in order
+                const int64_t jb = g.j_begin + (int64_t)s * g.split_len;
+                const int64_t je = jb + g.split_len < g.j_end ? jb + g.split_len : g.j_end;
+                int64_t placed = 0;
+                for (int64_t j = jb; j < je && placed < take; ++j) {
+                    if (j == i) continue;
+                    const double dx = a.xp[j] - xi, dy = a.xp[a.n + j] - yi,
+                                 dz = a.xp[2 * a.n + j] - zi;
+                    if (canon_r2f(dx, dy, dz) < rs2f) dst[placed++] = (int32_t)j;
+                }
+            }
+            start += c;
+        }
+        if (tid == 0) {
+            a.acc[b] = v[0];
+            a.acc[a.n_i + b] = v[1];
+            a.acc[2 * (int64_t)a.n_i + b] = v[2];
+            a.jerk[b] = v[3];
+            a.jerk[a.n_i + b] = v[4];
+            a.jerk[2 * (int64_t)a.n_i + b] = v[5];
+            a.nb_count[b] = (int32_t)total;
+            ovf = total > a.cap;
+            nonfin = !finite6(v[0], v[1], v[2], v[3], v[4], v[5]);
+            if (a.redo_k > 0.0 &&
+                needs_redo(a.redo_k, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]))
+                redo_push(a, b, g.j_begin, g.j_end);
+        }
+    } else if (tid == 0) {
+        for (int k = 0; k < 3; ++k) {
+            a.acc[(int64_t)k * a.n_i + b] = 0.0;
+            a.jerk[(int64_t)k * a.n_i + b] = 0.0;
+        }
+        a.nb_count[b] = 0;
+    }
+    flush_flags(a, ovf, bad && tid == 0, nonfin);
 }
 
 }  // namespace nb
