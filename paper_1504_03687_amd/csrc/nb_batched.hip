@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "nbreg.h"
+#include "nb_pair.h"
 #include "nb_rows.h"
 #include "nb_runtime.h"
 
@@ -41,7 +42,8 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A)
         const int64_t j1 = j0 + C.split_len < C.j_end ? j0 + C.split_len : C.j_end;
         const Dest d{C.splits == 1, C.slot_base + (int64_t)I.split * C.n_rows,
                      (int64_t)C.row_begin};
-        rows_pass<MIXED, IR>(A.f, tile, I.row0, (int64_t)C.row_begin + C.n_rows, j0, j1, d);
+        rows_pass<MIXED, IR>(A.f, tile, I.row0, (int64_t)C.row_begin + C.n_rows, j0, j1, d,
+                             C.near);
     }
 }
 
@@ -174,7 +176,7 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
         b.row_begin = (int32_t)c->i_off[k];
         b.n_rows = (int32_t)rc;
         b.splits = (int32_t)S;
-        b.pad = 0;
+        b.near = nc >= nb::kNearMinBodies ? nb::kNearFactor : 1.0f;
         b.slot_base = 0;
         if (S > 1) {
             b.slot_base = slots;

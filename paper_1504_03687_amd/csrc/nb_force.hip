@@ -39,7 +39,8 @@ __global__ __launch_bounds__(kBlock) void force_rows_kernel(ForceArgs a)
     const int64_t j0 = (int64_t)split * a.split_len;
     const int64_t j1 = j0 + a.split_len < a.n ? j0 + a.split_len : a.n;
     const Dest d{a.splits == 1, (int64_t)split * a.n_i, 0};
-    rows_pass<MIXED, IR>(a, tile, (int64_t)blockIdx.x * IR * kBlock, a.n_i, j0, j1, d);
+    rows_pass<MIXED, IR>(a, tile, (int64_t)blockIdx.x * IR * kBlock, a.n_i, j0, j1, d,
+                         a.near_factor);
 }
 
 // Wave w (global) handles row group w / splits (rows G*(w/splits) + g) over
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
                 rvz[g] = a.vp[2 * a.n + i];
                 rs2f[g] = (float)a.rs2[b];
                 hi[g] = cand_bound_f64(rs2f[g]);
-                candf[g] = cand_bound_f32(rs2f[g]);
+                candf[g] = cand_bound_f32(rs2f[g], a.near_factor);
                 if (d.direct) {
                     lst[g] = a.nb_list + b * (int64_t)a.cap;
                     lcap[g] = a.cap;

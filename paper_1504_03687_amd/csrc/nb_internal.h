@@ -59,6 +59,7 @@ struct ForceArgs {
     int32_t *redo_count;  // device counter, zeroed before the force kernel
     int32_t *redo_rows;   // [n_i]
     int32_t *redo_j0, *redo_j1;
+    float near_factor;    // mixed: FP64 near field below near_factor * rs2
     int32_t redo_groups;  // work-groups of the refinement kernel
     double *redo_part;    // [max(redo_groups, n_i)][6] chunk partials
 };
@@ -119,7 +120,7 @@ struct BCluster {
     int32_t row_begin;        // rows of the cluster
     int32_t n_rows;
     int32_t splits;
-    int32_t pad;
+    float near;               // mixed: near-field factor of this cluster
 };
 struct BItem {
     int32_t cluster;

@@ -156,10 +156,13 @@ __device__ __forceinline__ void add_term_f64(double &ax, double &ay, double &az,
     jz = __builtin_fma(q, dz, __builtin_fma(mr3, uz, jz));
 }
 
-// Mixed kernels evaluate pairs closer than sqrt(kNearFactor) neighbour radii
-// in FP64.  Those few pairs carry the largest terms, so their FP32 rounding
-// would dominate the error of a row whose sum cancels.
+// Mixed kernels evaluate pairs closer than sqrt(near) neighbour radii in FP64
+// (near = kNearFactor for large j-ranges, 1 otherwise: in a small cluster the
+// near pairs are a large share of all pairs and the FP64 branch would be taken
+// in most wave iterations).  Those few pairs carry the largest terms, so their
+// FP32 rounding would dominate the error of a row whose sum cancels.
 constexpr float kNearFactor = 4.0f;
+constexpr int64_t kNearMinBodies = int64_t(1) << 18;
 
 // Candidate bound for the FP64 plans: every canonical neighbour (and the self
 // pair, r2 = 0) has FP64 r2 < hi, so the exact canonical test only runs for
@@ -174,9 +177,9 @@ __device__ __forceinline__ double cand_bound_f64(float rs2f)
 // Candidate bound for the mixed plans, on r2f itself: the near-field bound
 // (neighbours included), or the smallest normal float when rs2 <= 0 so that
 // the self pair still enters.
-__device__ __forceinline__ float cand_bound_f32(float rs2f)
+__device__ __forceinline__ float cand_bound_f32(float rs2f, float near)
 {
-    const float h = rs2f * kNearFactor;
+    const float h = rs2f * near;
     return h > 1.17549435e-38f ? h : 1.17549435e-38f;
 }
 

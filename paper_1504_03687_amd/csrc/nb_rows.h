@@ -49,7 +49,7 @@ __device__ __forceinline__ int64_t dest_slot(const Dest &d, int64_t b)
 
 template <bool MIXED>
 __device__ __forceinline__ void row_init(Row<MIXED> &R, const ForceArgs &a, int64_t b,
-                                         int64_t row_end, const Dest &d)
+                                         int64_t row_end, const Dest &d, float near)
 {
     R.S.zero();
     R.cnt = 0;
@@ -73,7 +73,7 @@ __device__ __forceinline__ void row_init(Row<MIXED> &R, const ForceArgs &a, int6
     R.vz = a.vp[2 * a.n + i];
     R.rs2f = (float)a.rs2[b];
     R.hi = cand_bound_f64(R.rs2f);
-    R.candf = cand_bound_f32(R.rs2f);
+    R.candf = cand_bound_f32(R.rs2f, near);
     if (d.direct) {
         R.lst = a.nb_list + b * (int64_t)a.cap;
         R.lcap = a.cap;
@@ -219,12 +219,12 @@ __device__ __forceinline__ void flush_flags(const ForceArgs &a, bool ovf, bool b
 template <bool MIXED, int IR>
 __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTile],
                                           int64_t row0, int64_t row_end, int64_t j0,
-                                          int64_t j1, const Dest &d)
+                                          int64_t j1, const Dest &d, float near)
 {
     const int tid = threadIdx.x;
     Row<MIXED> R[IR];
 #pragma unroll
-    for (int r = 0; r < IR; ++r) row_init(R[r], a, row0 + r * kBlock + tid, row_end, d);
+    for (int r = 0; r < IR; ++r) row_init(R[r], a, row0 + r * kBlock + tid, row_end, d, near);
 
     const int64_t ntiles = j1 > j0 ? (j1 - j0 + kTile - 1) / kTile : 0;
     JBody nxt;

@@ -20,6 +20,7 @@
 
 #include "nbreg.h"
 #include "nb_internal.h"
+#include "nb_pair.h"
 #include "nb_runtime.h"
 
 using nb::Plan;
@@ -356,6 +357,7 @@ int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
     fa.splits = p.splits;
     fa.split_len = split_len;
     fa.redo_k = mixed ? redo_k(ctx) : 0.0;
+    fa.near_factor = n >= nb::kNearMinBodies ? nb::kNearFactor : 1.0f;
     const int32_t groups = nb::redo_groups_for(ctx->cu_count);
     const size_t redo_bytes = fa.redo_k > 0.0 ? nb::redo_scratch_bytes(n_i, groups) : 0;
     const size_t slot_bytes = nb::force_scratch_bytes(p, n_i);
