@@ -220,7 +220,9 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     const size_t b_mr = r256(std::max<size_t>(1, merge_rows.size()) * sizeof(int32_t));
     const size_t b_slots = nb::slot_scratch_bytes(slots);
     const int32_t groups = nb::redo_groups_for(ctx->cu_count);
-    const size_t b_redo = c->redo_k > 0.0 ? nb::redo_scratch_bytes(f.n_i, groups) : 0;
+    int64_t max_len = 1;
+    for (int32_t k = 0; k < C; ++k) max_len = std::max<int64_t>(max_len, c->j_off[k + 1] - c->j_off[k]);
+    const size_t b_redo = c->redo_k > 0.0 ? nb::redo_scratch_bytes(f.n_i, max_len) : 0;
     const size_t total = b_queue + b_cl + 2 * b_mr + b_it + b_slots + b_redo;
     if (ctx->scratch_limit && total > ctx->scratch_limit) return NB_ERR_OOM;
     hipError_t e = hipMalloc(&c->dmem, total);
@@ -261,7 +263,7 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     A.f = f;
     nb::bind_slot_scratch(A.f, slots, dslots);
     A.f.redo_k = c->redo_k;
-    if (c->redo_k > 0.0) nb::bind_redo_scratch(A.f, dredo, groups);
+    if (c->redo_k > 0.0) nb::bind_redo_scratch(A.f, dredo, groups, max_len);
     A.f.splits = 0;          // per-cluster
     A.f.split_len = 0;
     A.clusters = dcl;

@@ -204,35 +204,58 @@ __global__ __launch_bounds__(kBlock) void merge_wg_kernel(ForceArgs a)
     merge_row_wg(a, b, g, lds, scan);
 }
 
-// Refinement, pass 1: (row, chunk) items over a fixed grid of work-groups.
+__device__ __forceinline__ void write_forces(const ForceArgs &a, int64_t b, const double v[6])
+{
+    a.acc[b] = v[0];
+    a.acc[a.n_i + b] = v[1];
+    a.acc[2 * (int64_t)a.n_i + b] = v[2];
+    a.jerk[b] = v[3];
+    a.jerk[a.n_i + b] = v[4];
+    a.jerk[2 * (int64_t)a.n_i + b] = v[5];
+}
+
+// Refinement, pass 1: the first redo_rcap listed rows as (row, chunk) items
+// over the whole grid (chunk partials to scratch); any further rows one
+// work-group each, chunks in order.  Both give the same chunk-ordered sum.
 __global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
 {
     __shared__ double lds[kBlock / kWave];
     const int32_t count = __builtin_amdgcn_readfirstlane(*(volatile int32_t *)a.redo_count);
-    const int32_t cpr = redo_chunks(count, a.redo_groups);
-    const int64_t items = (int64_t)count * cpr;
-    for (int64_t it = blockIdx.x; it < items; it += gridDim.x)
-        redo_chunk(a, (int32_t)(it / cpr), (int32_t)(it % cpr), cpr, lds);
+    const int32_t par = count < a.redo_rcap ? count : a.redo_rcap;
+    const int32_t C = a.redo_chunks;
+    const int64_t items = (int64_t)par * C;
+    double v[6];
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        redo_chunk(a, (int32_t)(it / C), (int32_t)(it % C), lds, v);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) a.redo_part[it * 6 + k] = v[k];
+    }
+    for (int64_t q = (int64_t)par + blockIdx.x; q < count; q += gridDim.x) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int32_t c = 0; c < C; ++c) {
+            redo_chunk(a, (int32_t)q, c, lds, v);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[k] += v[k];
+        }
+        if (threadIdx.x == 0) write_forces(a, a.redo_rows[q], acc);
+    }
 }
 
-// Refinement, pass 2: sum each row's chunks in order and overwrite its forces.
+// Refinement, pass 2: sum each buffered row's chunks in order and overwrite
+// its forces.
 __global__ __launch_bounds__(256) void redo_final_kernel(ForceArgs a)
 {
     const int32_t count = *(volatile int32_t *)a.redo_count;
-    const int32_t cpr = redo_chunks(count, a.redo_groups);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count;
+    const int32_t par = count < a.redo_rcap ? count : a.redo_rcap;
+    const int32_t C = a.redo_chunks;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < par;
          q += (int64_t)gridDim.x * blockDim.x) {
         double v[6] = {0, 0, 0, 0, 0, 0};
-        for (int32_t c = 0; c < cpr; ++c)
+        for (int32_t c = 0; c < C; ++c)
 #pragma unroll
-            for (int k = 0; k < 6; ++k) v[k] += a.redo_part[(q * cpr + c) * 6 + k];
-        const int64_t b = a.redo_rows[q];
-        a.acc[b] = v[0];
-        a.acc[a.n_i + b] = v[1];
-        a.acc[2 * (int64_t)a.n_i + b] = v[2];
-        a.jerk[b] = v[3];
-        a.jerk[a.n_i + b] = v[4];
-        a.jerk[2 * (int64_t)a.n_i + b] = v[5];
+            for (int k = 0; k < 6; ++k) v[k] += a.redo_part[(q * C + c) * 6 + k];
+        write_forces(a, a.redo_rows[q], v);
     }
 }
 
@@ -256,15 +279,30 @@ size_t slot_scratch_bytes(int64_t slots)
 
 int32_t redo_groups_for(int cu_count) { return (cu_count > 0 ? cu_count : 256) * 4; }
 
-size_t redo_scratch_bytes(int32_t n_i, int32_t groups)
+static int32_t redo_chunks_for(int64_t max_len)
+{
+    const int64_t c = (max_len + kRedoChunk - 1) / kRedoChunk;
+    return (int32_t)(c > 0 ? c : 1);
+}
+
+static int32_t redo_rcap_for(int32_t n_i, int32_t chunks)
+{
+    int64_t r = kRedoPartItems / chunks;
+    if (r < 1) r = 1;
+    if (r > n_i) r = n_i > 0 ? n_i : 1;
+    return (int32_t)r;
+}
+
+size_t redo_scratch_bytes(int32_t n_i, int64_t max_len)
 {
     const int64_t rows = n_i > 0 ? n_i : 1;
-    const int64_t parts = rows > groups ? rows : groups;
+    const int32_t C = redo_chunks_for(max_len);
+    const int64_t parts = (int64_t)redo_rcap_for(n_i, C) * C;
     return 256 + 3 * round256((size_t)rows * sizeof(int32_t)) +
            round256((size_t)parts * 6 * sizeof(double));
 }
 
-void bind_redo_scratch(ForceArgs &a, void *base, int32_t groups)
+void bind_redo_scratch(ForceArgs &a, void *base, int32_t groups, int64_t max_len)
 {
     char *p = (char *)base;
     const size_t arr = round256((size_t)(a.n_i > 0 ? a.n_i : 1) * sizeof(int32_t));
@@ -274,6 +312,8 @@ void bind_redo_scratch(ForceArgs &a, void *base, int32_t groups)
     a.redo_j1 = (int32_t *)(p + 256 + 2 * arr);
     a.redo_part = (double *)(p + 256 + 3 * arr);
     a.redo_groups = groups;
+    a.redo_chunks = redo_chunks_for(max_len);
+    a.redo_rcap = redo_rcap_for(a.n_i, a.redo_chunks);
 }
 
 hipError_t launch_redo(const ForceArgs &a, hipStream_t s)

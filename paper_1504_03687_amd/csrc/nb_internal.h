@@ -61,16 +61,24 @@ struct ForceArgs {
     int32_t *redo_j0, *redo_j1;
     float near_factor;    // mixed: FP64 near field below near_factor * rs2
     int32_t redo_groups;  // work-groups of the refinement kernel
-    double *redo_part;    // [max(redo_groups, n_i)][6] chunk partials
+    int32_t redo_chunks;  // chunks per refined row (j-range / kRedoChunk, rounded up)
+    int32_t redo_rcap;    // rows refined through the chunk-partials buffer
+    double *redo_part;    // [redo_rcap][redo_chunks][6] chunk partials
 };
+
+// Refinement works on fixed chunks of kRedoChunk bodies so that a refined
+// row's FP64 sum does not depend on how many rows were refined in the call.
+constexpr int64_t kRedoChunk = 8192;
+constexpr int64_t kRedoPartItems = int64_t(1) << 20;   // chunk partials held at most
 
 // Components per slot: acc x,y,z, jerk x,y,z, and the two error-scale sums.
 constexpr int kSlotComp = 8;
 // Extra scratch for the redo list of n_i rows (counter, row / j-range arrays
 // and the chunk partials of 'groups' refinement work-groups).
 int32_t redo_groups_for(int cu_count);
-size_t redo_scratch_bytes(int32_t n_i, int32_t groups);
-void bind_redo_scratch(ForceArgs &a, void *base, int32_t groups);
+// max_len: longest j-range of any row of the launch
+size_t redo_scratch_bytes(int32_t n_i, int64_t max_len);
+void bind_redo_scratch(ForceArgs &a, void *base, int32_t groups, int64_t max_len);
 hipError_t launch_redo(const ForceArgs &a, hipStream_t s);
 
 struct Plan {

@@ -398,23 +398,16 @@ __device__ __forceinline__ double block_sum(double v, double *lds /* [kBlock / k
     return t;
 }
 
-// Refinement: chunks per listed row so that 'groups' work-groups are busy.
-__device__ __forceinline__ int32_t redo_chunks(int32_t count, int32_t groups)
-{
-    const int32_t c = count > 0 ? groups / count : 1;
-    return c < 1 ? 1 : (c > 256 ? 256 : c);
-}
-
-// FP64 sums of one chunk of one listed row by a whole work-group (forces only;
-// the row's neighbour list and count are already final).
-__device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_t c,
-                                          int32_t cpr, double *lds)
+// FP64 sums over one fixed chunk [j0 + c*kRedoChunk, ...) of a refined row's
+// j-range, by a whole work-group in a fixed pattern; every lane returns the
+// six sums (acc, jerk).  Chunks past the row's range are empty (zero).
+__device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_t c, double *lds,
+                                          double out[6])
 {
     const int64_t b = a.redo_rows[q];
     const int64_t j0 = a.redo_j0[q], j1 = a.redo_j1[q];
-    const int64_t clen = ((j1 - j0 + cpr - 1) / cpr + kWave - 1) / kWave * kWave;
-    const int64_t cj0 = j0 + (int64_t)c * clen;
-    const int64_t cj1 = cj0 + clen < j1 ? cj0 + clen : j1;
+    const int64_t cj0 = j0 + (int64_t)c * kRedoChunk;
+    const int64_t cj1 = cj0 + kRedoChunk < j1 ? cj0 + kRedoChunk : j1;
     const int64_t i = a.i_block[b];
     const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
     const double vxi = a.vp[i], vyi = a.vp[a.n + i], vzi = a.vp[2 * a.n + i];
@@ -436,12 +429,8 @@ __device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_
         accum_f64(S, dx, dy, dz, r2, J.vx - vxi, J.vy - vyi, J.vz - vzi, J.m, excl);
     }
     const double v[6] = {S.ax, S.ay, S.az, S.jx, S.jy, S.jz};
-    double *out = a.redo_part + ((int64_t)q * cpr + c) * 6;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const double t = block_sum(v[k], lds);
-        if (threadIdx.x == 0) out[k] = t;
-    }
+    for (int k = 0; k < 6; ++k) out[k] = block_sum(v[k], lds);
 }
 
 // Merge of one row by a whole work-group, for plans with many splits: lane t

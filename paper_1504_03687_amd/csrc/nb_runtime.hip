@@ -359,14 +359,14 @@ int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
     fa.redo_k = mixed ? redo_k(ctx) : 0.0;
     fa.near_factor = n >= nb::kNearMinBodies ? nb::kNearFactor : 1.0f;
     const int32_t groups = nb::redo_groups_for(ctx->cu_count);
-    const size_t redo_bytes = fa.redo_k > 0.0 ? nb::redo_scratch_bytes(n_i, groups) : 0;
+    const size_t redo_bytes = fa.redo_k > 0.0 ? nb::redo_scratch_bytes(n_i, n) : 0;
     const size_t slot_bytes = nb::force_scratch_bytes(p, n_i);
     if (redo_bytes + slot_bytes > 0) {
         int rc = ensure_scratch(ctx, redo_bytes + slot_bytes);
         if (rc != NB_OK) return rc;
     }
     if (redo_bytes) {
-        nb::bind_redo_scratch(fa, ctx->scratch, groups);
+        nb::bind_redo_scratch(fa, ctx->scratch, groups, n);
         e = hipMemsetAsync(fa.redo_count, 0, sizeof(int32_t), ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e);
     }
