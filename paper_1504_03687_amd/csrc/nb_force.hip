@@ -225,11 +225,14 @@ __global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
     const int32_t C = a.redo_chunks;
     const int64_t items = (int64_t)par * C;
     double v[6];
+    // chunk-major order: work-groups running at the same time share a chunk
+    // of bodies (L2 reuse across the refined rows)
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        redo_chunk(a, (int32_t)(it / C), (int32_t)(it % C), lds, v);
+        const int32_t c = (int32_t)(it / par), q = (int32_t)(it % par);
+        redo_chunk(a, q, c, lds, v);
         if (threadIdx.x == 0)
 #pragma unroll
-            for (int k = 0; k < 6; ++k) a.redo_part[it * 6 + k] = v[k];
+            for (int k = 0; k < 6; ++k) a.redo_part[((int64_t)q * C + c) * 6 + k] = v[k];
     }
     for (int64_t q = (int64_t)par + blockIdx.x; q < count; q += gridDim.x) {
         double acc[6] = {0, 0, 0, 0, 0, 0};
