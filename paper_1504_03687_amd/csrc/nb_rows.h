@@ -433,10 +433,10 @@ __device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_
     for (int k = 0; k < 6; ++k) out[k] = block_sum(v[k], lds);
 }
 
-// Merge of one row by a whole work-group, for plans with many splits: lane t
-// owns the contiguous splits [t*K, (t+1)*K), so summation order and list order
-// are fixed; a work-group prefix scan of the lanes' counts places the
-// segments.
+// Merge of one row by a whole work-group, for plans with many splits: the
+// sums stride the splits over the lanes (fixed order); for the lists lane t
+// owns the contiguous splits [t*K, (t+1)*K) and a work-group prefix scan of
+// the lanes' counts places its segments, so the list stays in split order.
 __device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, const MergeGeom &g,
                                              double *lds, int64_t *scan)
 {
@@ -449,14 +449,17 @@ __device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, cons
     const int32_t s0 = tid * K;
     const int32_t s1 = s0 + K < S ? s0 + K : S;
 
+    // sums: lanes stride the splits (coalesced loads), fixed order
     double v[kSlotComp] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t mine = 0;
-    for (int32_t s = s0; s < s1; ++s) {
+    for (int32_t s = tid; s < S; s += kBlock) {
         const int64_t slot = g.slot0 + (int64_t)s * g.slot_step;
 #pragma unroll
         for (int k = 0; k < kSlotComp; ++k) v[k] += a.part[(int64_t)k * T + slot];
-        mine += a.seg_cnt[slot];
     }
+    // counts: lane t owns the contiguous splits [s0, s1) so that its segments
+    // are consecutive in the row's list
+    int64_t mine = 0;
+    for (int32_t s = s0; s < s1; ++s) mine += a.seg_cnt[g.slot0 + (int64_t)s * g.slot_step];
 #pragma unroll
     for (int k = 0; k < kSlotComp; ++k) v[k] = block_sum(v[k], lds);
 
