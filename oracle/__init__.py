@@ -18,6 +18,9 @@ Parity status per function (what pins it; see tests/test_oracle_pins.py):
   local_loss       -- linear in m; equals the sum of pair losses (pinned)
   hermite_correct  -- exact for cubic force histories, two-body orbit
                       convergence at fourth order (pinned)
+  sched.*          -- sorting-list selection of active bodies (oracle/sched.py):
+                      hand-worked golden list, pairwise order, exact rational
+                      block-step simulation (pinned)
 """
 from __future__ import annotations
 

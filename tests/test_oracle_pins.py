@@ -384,3 +384,101 @@ def test_hermite_two_body_orbit_fourth_order():
         return np.abs(x - np.array([[0.5, -0.5], [0, 0], [0, 0]])).max()
     e1, e2 = run(200), run(400)
     assert e1 < 1e-5 and 12 < e1 / e2 < 20, (e1, e2)
+
+
+# --------------------------------------------------------------------------- #
+# sorting-list selection of active bodies (section 3.3.1)
+# --------------------------------------------------------------------------- #
+def _golden_sched():
+    with open(os.path.join(GOLDEN, "sorting_list.json")) as f:
+        return json.load(f)
+
+
+def test_sorting_list_golden():
+    """Hand-worked list, offsets, block sequence and post-update level sets."""
+    import oracle.sched as S
+    g = _golden_sched()
+    lev = np.array(g["levels"])
+    order, le = S.sort_list(lev, g["k_max"])
+    assert order.tolist() == g["order"] and le.tolist() == g["level_end"]
+    t = np.zeros(lev.size)
+    dt = np.ldexp(1.0, -lev)
+    t_now = 0.0
+    for blk in g["blocks_from_t0"]:
+        t_new, act = S.next_block(t, dt)
+        assert t_new == blk["t_new"] and act.tolist() == blk["active"]
+        L = S.due_level(t_new, g["k_max"])
+        assert L == blk["level"]
+        assert sorted(order[: le[L]].tolist()) == blk["active"]
+        # the next block time is the current one plus the smallest step
+        assert t_new == t_now + math.ldexp(1.0, -int(lev.max()))
+        t[act] = t_new
+        t_now = t_new
+    assert t_now == g["update_at_t"] and S.due_level(t_now, g["k_max"]) == g["update_level"]
+    new = np.array(g["new_levels"])
+    order2, le2 = S.sort_list(new, g["k_max"])
+    assert le2.tolist() == g["new_level_end"]
+    for L, members in g["new_level_sets"].items():
+        L = int(L)
+        assert sorted(order2[le2[L + 1]: le2[L]].tolist()) == members
+    t_new, act = S.next_block(t, np.ldexp(1.0, -new))
+    nxt = g["next_after_update"]
+    assert t_new == nxt["t_new"] and act.tolist() == nxt["active"]
+    assert S.due_level(t_new, g["k_max"]) == nxt["level"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sorting_list_pairwise_and_counts(seed):
+    """Brute force on small random inputs: the list is a permutation, every
+    pair of list positions is ordered by (level descending, index ascending),
+    and every offset equals a direct count."""
+    import oracle.sched as S
+    rng = np.random.default_rng(600 + seed)
+    n = [0, 1, 7, 64, 129, 300][seed]
+    k_max = [0, 3, 5, 9, 20, 63][seed]
+    lev = rng.integers(0, k_max + 1, n)
+    order, le = S.sort_list(lev, k_max)
+    assert sorted(order.tolist()) == list(range(n))
+    for p in range(n):
+        for q in range(p + 1, n):
+            a, b = int(order[p]), int(order[q])
+            assert lev[a] > lev[b] or (lev[a] == lev[b] and a < b)
+    assert le.size == k_max + 2 and le[k_max + 1] == 0
+    for L in range(k_max + 1):
+        assert le[L] == sum(1 for v in lev.tolist() if v >= L)
+    with pytest.raises(ValueError):
+        S.sort_list(np.array([k_max + 1]), k_max)
+
+
+def test_block_step_selection_exact_rational():
+    """Synchronised block steps simulated in exact rationals: the brute-force
+    next block time and active set agree with the exact ones, the active set is
+    every body whose level is at least the coarsest level dividing the block
+    time, and the block time advances by the smallest step."""
+    import oracle.sched as S
+    rng = np.random.default_rng(612)
+    n, k_max = 97, 12
+    lev = rng.integers(2, k_max + 1, n)
+    t_ex = [Fraction(0)] * n
+    t_now = Fraction(0)
+    for step in range(400):
+        dt_ex = [Fraction(1, 2 ** int(k)) for k in lev]
+        nxt = [a + b for a, b in zip(t_ex, dt_ex)]
+        T = min(nxt)
+        act_ex = [i for i in range(n) if nxt[i] == T]
+        t_new, act = S.next_block(np.array([float(a) for a in t_ex]),
+                                  np.ldexp(1.0, -lev))
+        assert Fraction(t_new) == T and act.tolist() == act_ex
+        assert T == t_now + Fraction(1, 2 ** int(lev.max()))
+        L = S.due_level(t_new, k_max)
+        assert T.denominator == 2 ** L
+        assert act_ex == [i for i in range(n) if lev[i] >= L]
+        for i in act_ex:
+            t_ex[i] = T
+            # new level: commensurate with T (>= L), within [0, k_max]
+            lo = max(L, int(lev[i]) - 1)
+            hi = min(k_max, int(lev[i]) + 2)
+            lev[i] = int(rng.integers(lo, hi + 1))
+        t_now = T
+    assert S.due_level(1.0, 8) == 0 and S.due_level(0.375, 8) == 3
+    assert S.due_level(0.5, 8) == 1 and S.due_level(2.0 ** -9, 8) == -1
