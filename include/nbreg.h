@@ -60,8 +60,11 @@ enum {
 enum {
     NB_STATUS_OVERFLOW = 1,  /* some row has more neighbours than nb_cap       */
     NB_STATUS_BAD_INDEX = 2, /* some i_block entry outside [0, n); row zeroed  */
-    NB_STATUS_NONFINITE = 4  /* some output is Inf/NaN (e.g. coincident bodies */
+    NB_STATUS_NONFINITE = 4, /* some output is Inf/NaN (e.g. coincident bodies */
                              /* outside each other's radius)                   */
+    NB_STATUS_BAD_LEVEL = 8  /* scheduler: a step level or list entry out of   */
+                             /* range, or a prefix that is not the due block;  */
+                             /* the list and offsets were left unchanged       */
 };
 
 /* ---- context ------------------------------------------------------------ */
@@ -95,7 +98,7 @@ int nb_ctx_set_scratch_limit(nb_ctx *ctx, int64_t bytes);
  * launch count of one kernel class since the last reset (class 0 = regular
  * force main kernel, 1 = cross-split reduce, 2 = predictor, 3 = adjoint,
  * 4 = batched, 5 = mixed-precision FP64 refinement, 6 = irregular force
- * and potential). */
+ * and potential, 7 = block-step scheduler). */
 int nb_ctx_enable_timing(nb_ctx *ctx, int on);
 int nb_ctx_kernel_time(nb_ctx *ctx, int kernel_class, double *ms, int64_t *launches);
 int nb_ctx_reset_timing(nb_ctx *ctx);
@@ -228,6 +231,49 @@ int nb_hermite_correct(nb_ctx *ctx, int64_t n, const double *h, const double *x0
  * double) = 1/2 sum_i m_i phi_i, reduced in a fixed order. */
 int nb_potential(nb_ctx *ctx, int64_t n, const double *x, const double *m, double *phi,
                  double *energy);
+
+/* ---- block-step scheduler: the sorting list (section 3.3.1) ------------- */
+
+/* Every body has a step 2^-level[j] (level in [0, k_max], k_max <= 63).  The
+ * sorting list is the body index list ordered by step from the smallest to
+ * the largest (level descending), with boundary offsets
+ *   level_end[L] = number of bodies with level >= L,  L = 0 .. k_max+1,
+ * so the bodies of level L are order[level_end[L+1] : level_end[L]]; the
+ * paper's I_off(L), the last list position of step 2^-L, is level_end[L]-1.
+ * With synchronised block steps (every body's time a multiple of its step)
+ * the bodies due at a block time whose coarsest dividing step is 2^-L are
+ * the prefix order[0 : level_end[L]], which can be passed as i_block as is.
+ *
+ * nb_sched_build: full build from level[n] (device).  order [n] and level_end
+ * [k_max+2] (device) are overwritten; bodies of equal level are listed by
+ * ascending index.  A level outside [0, k_max] sets NB_STATUS_BAD_LEVEL and
+ * leaves order and level_end unchanged.  Errors: n <= 0 or n > INT32_MAX,
+ * k_max outside [0, 63], NULL required pointer. */
+int nb_sched_build(nb_ctx *ctx, int64_t n, const int32_t *level, int32_t k_max, int32_t *order,
+                   int32_t *level_end, uint32_t *status);
+
+/* nb_sched_update: after the block of level L (the n_active = level_end[L]
+ * bodies order[0 : n_active]) has been integrated and level[] holds their
+ * new levels, re-sorts that prefix by the new levels and rewrites
+ * level_end[L .. k_max+1]; the rest of the list and level_end[0 .. L-1] are
+ * untouched.  O(n_active) work.  A new step must divide the block time, so
+ * every new level must lie in [L, k_max]; bodies of one level may come out in
+ * any order.  If a new level is out of that range, a list entry is outside
+ * [0, n), or level_end[L] != n_active, NB_STATUS_BAD_LEVEL is set and order
+ * and level_end are left unchanged.  n_active == 0 is a no-op.  Errors: as
+ * nb_sched_build, plus L outside [0, k_max] or n_active outside [0, n]. */
+int nb_sched_update(nb_ctx *ctx, int64_t n, int32_t n_active, int32_t L, const int32_t *level,
+                    int32_t k_max, int32_t *order, int32_t *level_end, uint32_t *status);
+
+/* nb_sched_next (host only, no GPU work): the offset search of Figure 1.
+ * From the current block time t_now and a HOST copy of level_end, the
+ * smallest step is that of the deepest occupied level kd, the next block time
+ * is *t_new = t_now + 2^-kd, *level = the coarsest L whose step 2^-L divides
+ * *t_new, and *n_active = level_end[L].  Errors (NB_ERR_INVALID_ARG): an
+ * empty or non-monotone level_end, t_now negative, non-finite or not a
+ * multiple of 2^-kd, or t_now too large for 2^-kd to change it. */
+int nb_sched_next(double t_now, int32_t k_max, const int32_t *level_end_host, double *t_new,
+                  int32_t *level, int32_t *n_active);
 
 #ifdef __cplusplus
 }

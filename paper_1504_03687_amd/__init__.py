@@ -25,14 +25,15 @@ import torch
 __all__ = [
     "NbError", "Context", "lib", "library_path", "context", "predict", "regular_force",
     "regular_force_adjoint", "regular_force_batched", "autotune", "RegularForce",
-    "irregular_force", "hermite_correct", "potential",
-    "FP64", "MIXED", "STATUS_OVERFLOW", "STATUS_BAD_INDEX", "STATUS_NONFINITE",
+    "irregular_force", "hermite_correct", "potential", "sched_build", "sched_update",
+    "sched_next", "FP64", "MIXED", "STATUS_OVERFLOW", "STATUS_BAD_INDEX",
+    "STATUS_NONFINITE", "STATUS_BAD_LEVEL",
 ]
 
 FP64, MIXED = 0, 1
-STATUS_OVERFLOW, STATUS_BAD_INDEX, STATUS_NONFINITE = 1, 2, 4
+STATUS_OVERFLOW, STATUS_BAD_INDEX, STATUS_NONFINITE, STATUS_BAD_LEVEL = 1, 2, 4, 8
 (CLASS_FORCE, CLASS_MERGE, CLASS_PREDICT, CLASS_ADJOINT, CLASS_BATCHED, CLASS_REDO,
- CLASS_STEP) = range(7)
+ CLASS_STEP, CLASS_SCHED) = range(8)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # NBREG_LIBRARY may point at another build of the same library (e.g. a
@@ -93,6 +94,10 @@ def lib() -> C.CDLL:
                                    C.c_int),
             "nb_hermite_correct": ([vp, i64] + [vp] * 11, C.c_int),
             "nb_potential": ([vp, i64, vp, vp, vp, vp], C.c_int),
+            "nb_sched_build": ([vp, i64, vp, i32, vp, vp, u32p], C.c_int),
+            "nb_sched_update": ([vp, i64, i32, i32, vp, i32, vp, vp, u32p], C.c_int),
+            "nb_sched_next": ([dbl, i32, vp, C.POINTER(dbl), C.POINTER(i32),
+                               C.POINTER(i32)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -403,6 +408,53 @@ def potential(x, m, ctx: Context | None = None):
     _check(lib().nb_potential(ctx.handle, n, _ptr(x), _ptr(m), _ptr(phi), _ptr(U)),
            "nb_potential")
     return phi, U
+
+
+def sched_build(level, k_max: int, order=None, level_end=None, status=None,
+                ctx: Context | None = None):
+    """Sorting list of the bodies by step (level descending, ties by index)
+    and its offsets: returns (order (n,) int32, level_end (k_max+2,) int32),
+    both on the GPU; level_end[L] = number of bodies with level >= L."""
+    n = level.shape[0]
+    _dev(level, "level", torch.int32, (n,))
+    order = torch.empty(n, dtype=torch.int32, device=level.device) if order is None else \
+        _dev(order, "order", torch.int32, (n,))
+    level_end = torch.empty(k_max + 2, dtype=torch.int32, device=level.device) \
+        if level_end is None else _dev(level_end, "level_end", torch.int32, (k_max + 2,))
+    if status is not None:
+        _dev(status, "status", torch.int32, (1,))
+    ctx = ctx or context(level.device.index)
+    ctx._bind_stream()
+    _check(lib().nb_sched_build(ctx.handle, n, _ptr(level), int(k_max), _ptr(order),
+                                _ptr(level_end), _ptr(status)), "nb_sched_build")
+    return order, level_end
+
+
+def sched_update(order, level_end, n_active: int, L: int, level, k_max: int, status=None,
+                 ctx: Context | None = None):
+    """In place: re-sorts the due prefix order[:n_active] (block level L) by
+    the bodies' new levels and rewrites level_end[L:]."""
+    n = level.shape[0]
+    _dev(level, "level", torch.int32, (n,))
+    _dev(order, "order", torch.int32, (n,))
+    _dev(level_end, "level_end", torch.int32, (k_max + 2,))
+    if status is not None:
+        _dev(status, "status", torch.int32, (1,))
+    ctx = ctx or context(level.device.index)
+    ctx._bind_stream()
+    _check(lib().nb_sched_update(ctx.handle, n, int(n_active), int(L), _ptr(level),
+                                 int(k_max), _ptr(order), _ptr(level_end), _ptr(status)),
+           "nb_sched_update")
+
+
+def sched_next(t_now: float, k_max: int, level_end_host):
+    """Host offset search: (t_new, L, n_active) of the next block from a host
+    copy of level_end (sequence of k_max+2 ints)."""
+    le = (C.c_int32 * (k_max + 2))(*[int(v) for v in level_end_host])
+    t_new, L, n_a = C.c_double(), C.c_int32(), C.c_int32()
+    _check(lib().nb_sched_next(float(t_now), int(k_max), C.cast(le, C.c_void_p),
+                               C.byref(t_new), C.byref(L), C.byref(n_a)), "nb_sched_next")
+    return t_new.value, L.value, n_a.value
 
 
 class RegularForce(torch.autograd.Function):

@@ -20,7 +20,8 @@ enum {
     NB_CLASS_BATCHED = 4,
     NB_CLASS_REDO = 5,
     NB_CLASS_STEP = 6,
-    NB_NCLASS = 7
+    NB_CLASS_SCHED = 7,
+    NB_NCLASS = 8
 };
 
 namespace nbrt {

@@ -112,3 +112,67 @@ def test_argument_validation_adjoint_batched_autotune(host_ctx):
     assert bat(lst=None) == E and bat(lst=None, cap=0) == -4
     assert L.nb_autotune(host_ctx, 10, None, 0) == E
     assert L.nb_autotune(host_ctx, 4096, None, 0) == -4
+
+
+def test_argument_validation_scheduler(host_ctx):
+    L = nb.lib()
+    p = _fake
+    E, U = -1, -4
+
+    def build(ctx=host_ctx, n=100, lev=p(1), k_max=20, order=p(2), le=p(3)):
+        return L.nb_sched_build(ctx, n, lev, k_max, order, le, None)
+
+    def update(ctx=host_ctx, n=100, n_a=10, lvl=3, lev=p(1), k_max=20, order=p(2), le=p(3)):
+        return L.nb_sched_update(ctx, n, n_a, lvl, lev, k_max, order, le, None)
+
+    assert build(ctx=None) == E and build(n=0) == E and build(n=2 ** 31) == E
+    assert build(k_max=-1) == E and build(k_max=64) == E
+    assert build(lev=None) == E and build(order=None) == E and build(le=None) == E
+    assert build() == U and build(k_max=63) == U          # valid; no device
+    assert update(lvl=-1) == E and update(lvl=21) == E
+    assert update(n_a=-1) == E and update(n_a=101) == E and update(k_max=64) == E
+    assert update(order=None) == E and update(le=None) == E
+    assert update() == U
+
+
+def _next(t_now, k_max, le):
+    t, lv, na = C.c_double(), C.c_int32(), C.c_int32()
+    arr = (C.c_int32 * len(le))(*le)
+    rc = nb.lib().nb_sched_next(float(t_now), k_max, C.cast(arr, C.c_void_p), C.byref(t),
+                                C.byref(lv), C.byref(na))
+    return rc, t.value, lv.value, na.value
+
+
+def test_sched_next_rejects_bad_offsets():
+    assert _next(0.0, 3, [5, 4, 2, 1, 0])[0] == 0
+    assert _next(0.0, 3, [0, 0, 0, 0, 0])[0] == -1        # empty
+    assert _next(0.0, 3, [5, 4, 2, 3, 0])[0] == -1        # not monotone
+    assert _next(0.0, 3, [5, 4, 2, 1, 1])[0] == -1        # level_end[k_max+1] != 0
+    assert _next(-1.0, 3, [5, 4, 2, 1, 0])[0] == -1
+    assert _next(float("inf"), 3, [5, 4, 2, 1, 0])[0] == -1
+    assert _next(0.0625, 3, [5, 4, 2, 1, 0])[0] == -1     # not a multiple of 2^-3
+    assert _next(2.0 ** 60, 3, [5, 4, 2, 1, 0])[0] == -1  # step below resolution
+    assert _next(0.0, -1, [0])[0] == -1 and _next(0.0, 64, [0] * 66)[0] == -1
+
+
+def test_sched_next_matches_oracle_selection():
+    """The host offset search (Figure 1) against the oracle's brute-force
+    selection over all bodies, along a seeded synchronised block-step run."""
+    import numpy as np
+    import oracle.sched as S
+    rng = np.random.default_rng(701)
+    n, k_max = 500, 16
+    lev = rng.integers(3, 12, n)
+    t = np.zeros(n)
+    t_now = 0.0
+    for step in range(3000):
+        _, le = S.sort_list(lev, k_max)
+        rc, t_new, L, n_a = _next(t_now, k_max, le.tolist())
+        assert rc == 0
+        ot, act = S.next_block(t, np.ldexp(1.0, -lev))
+        assert t_new == ot and L == S.due_level(ot, k_max) and n_a == act.size
+        for i in act:
+            lo = max(L, int(lev[i]) - 1)
+            lev[i] = int(rng.integers(lo, min(k_max, int(lev[i]) + 2) + 1))
+        t[act] = t_new
+        t_now = t_new

@@ -275,6 +275,30 @@ def level_weight(L: int, k_min: int = 3) -> int:
     return 1 if L == k_min else 2 ** (L - k_min - 1)
 
 
+def sample_levels(rng: np.random.Generator, n: int, k_lo: int, k_hi: int, k_peak: float,
+                  width: float = 1.5, deep_frac: float = 0.05) -> np.ndarray:
+    """Synthetic step levels in [k_lo, k_hi]: a bulk around k_peak (rounded
+    normal of the given width) plus a fraction deep_frac spread uniformly over
+    the deeper levels, the shape of a cluster's step distribution with a tail of
+    close pairs and binaries."""
+    k = np.rint(rng.normal(k_peak, width, n))
+    deep = rng.random(n) < deep_frac
+    k[deep] = rng.integers(int(k_peak) + 1, k_hi + 1, int(deep.sum()))
+    return np.clip(k, k_lo, k_hi).astype(np.int32)
+
+
+def next_levels(rng: np.random.Generator, lev: np.ndarray, L: int, k_max: int,
+                p_keep: float = 0.7) -> np.ndarray:
+    """New levels for bodies of a block of level L: kept with probability
+    p_keep, else one coarser or one to three finer, clamped to [L, k_max] (a new
+    step must divide the block time)."""
+    lev = np.asarray(lev, np.int64)
+    u = rng.random(lev.size)
+    d = np.where(u < p_keep, 0, np.where(u < p_keep + (1 - p_keep) / 2, -1,
+                                         rng.integers(1, 4, lev.size)))
+    return np.clip(lev + d, L, k_max).astype(np.int32)
+
+
 # --------------------------------------------------------------------------- #
 # named workloads
 # --------------------------------------------------------------------------- #
