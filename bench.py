@@ -265,6 +265,57 @@ def main():
             log(f"batched {prec}: {ms:.2f} ms, {pairs4 / ms * 1e-6:.1f} G pairs/s")
             del o4
 
+    # sorting-list scheduler (section 3.3.1) on the same cluster's step levels:
+    # full build, then the O(N_i) update of each level's block, weighted by how
+    # often each level is due in one 2^-3 cycle of the hierarchy
+    if not args.no_levels:
+        k_max = 20
+        lev_h = s["levels"].astype(np.int32)
+        lev_d = dev(lev_h)
+        order_d, le_d = nb.sched_build(lev_d, k_max, ctx=ctx)
+        torch.cuda.synchronize()
+        ctx.reset_timing()
+        ctx.enable_timing(True)
+        c1 = time.perf_counter()
+        for _ in range(10):
+            nb.sched_build(lev_d, k_max, order=order_d, level_end=le_d, ctx=ctx)
+        torch.cuda.synchronize()
+        b_wall = (time.perf_counter() - c1) * 1e6 / 10
+        bms, bl = ctx.kernel_time(nb.CLASS_SCHED)
+        b_us = bms * 1e3 / max(bl, 1)
+        le_h = le_d.cpu().numpy()
+        per_level, cyc_us, cyc_bodies = {}, 0.0, 0
+        for L in range(3, k_max + 1):
+            n_a = int(le_h[L])
+            if n_a == 0:
+                continue
+            ctx.reset_timing()
+            reps = 20
+            c1 = time.perf_counter()
+            for _ in range(reps):
+                nb.sched_update(order_d, le_d, n_a, L, lev_d, k_max, ctx=ctx)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - c1) * 1e6 / reps
+            ums, ul = ctx.kernel_time(nb.CLASS_SCHED)
+            us = ums * 1e3 / max(ul, 1)
+            per_level[str(L)] = {"n_active": n_a, "update_us": round(us, 2),
+                                 "wall_us": round(wall, 2),
+                                 "GB_per_s": round(28.0 * n_a / us * 1e-3, 1)}
+            cyc_us += W.level_weight(L) * us
+            cyc_bodies += W.level_weight(L) * n_a
+        ctx.enable_timing(False)
+        blocks = sum(W.level_weight(L) for L in range(3, k_max + 1) if str(L) in per_level)
+        extras["sched"] = {
+            "workload": f"N={n} step levels 3..20 of the same cluster, k_max {k_max}",
+            "build_us": round(b_us, 2), "build_wall_us": round(b_wall, 2),
+            "build_GB_per_s": round(12.0 * n / b_us * 1e-3, 1),
+            "update_per_level": per_level,
+            "cycle": {"blocks": blocks, "active_bodies": cyc_bodies,
+                      "update_ms": round(cyc_us * 1e-3, 3),
+                      "mean_update_us": round(cyc_us / max(blocks, 1), 2)}}
+        log(f"sched: build {b_us:.1f} us, cycle of {blocks} blocks: update "
+            f"{cyc_us * 1e-3:.2f} ms ({cyc_us / max(blocks, 1):.1f} us/block)")
+
     # CPU oracle on a bounded sample of the same full block
     cpu = None
     if args.cpu_rows > 0:
@@ -281,6 +332,16 @@ def main():
                "sample": f"{rows.size} random rows of the N=2^20 full block against all "
                          f"{n} bodies ({rows.size * (n - 1):.3g} pairs, {dt:.1f}s, FP64)"}
         log(f"cpu oracle: {cpu['value']} G pairs/s on {threads} threads")
+        if "sched" in extras:
+            # the oracle's plain O(N) search for the next block over all bodies
+            import oracle.sched as osched
+            tt = np.zeros(n)
+            dts = np.ldexp(1.0, -s["levels"].astype(np.int64))
+            c1 = time.perf_counter()
+            for _ in range(5):
+                osched.next_block(tt, dts)
+            extras["sched"]["cpu_oracle_full_search_ms"] = round(
+                (time.perf_counter() - c1) * 1e3 / 5, 3)
 
     head = res.get("mixed") or res["fp64"]
     dom = "mixed" if "mixed" in res else "fp64"

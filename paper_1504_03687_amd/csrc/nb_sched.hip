@@ -16,16 +16,21 @@
 // after an update follows the counting sort of the prefix (the paper allows
 // giving up stability); the full build is stable (ties by ascending index).
 //
-// GPU shape (both entries): a counting sort by level.
-//   count:   4096 items per work-group; wave-aggregated LDS histogram per
-//            work-group, stored level-major [K][blocks], plus global totals;
-//            range checks raise a flag that makes the later kernels no-ops;
-//   offsets: one wave per level; exclusive scan of its row of block counts
-//            plus the count of all deeper levels; writes level_end;
-//   scatter: ranks within a work-group from per-wave ballots, combined in LDS
-//            over (round, wave) in item order, so the result is deterministic
-//            and, for the build, stable;
-//   copy:    (update only) the re-sorted prefix back into the list.
+// GPU shape: a counting sort by level, deterministic.  Each wave owns a
+// contiguous run of items and walks it in rounds of 64: per round, one ballot
+// per distinct level gives every item its rank among the wave's earlier items
+// of that level (a running per-wave count in LDS); the per-level wave counts
+// are then scanned across waves (and work-groups) in item order, so the
+// build is stable.  All rounds' gathers are issued before any is used.
+//   <= 16384 items: one work-group of 1024 threads does the whole sort in one
+//            launch, in place (every read of the list precedes the first
+//            write);
+//   larger:  two launches: count (4096 items per work-group: per-level
+//            counts stored level-major [K][blocks], a per-block range flag,
+//            and for an update a copy of the prefix), then scatter (each
+//            work-group sums the count rows it needs for its own offsets, so
+//            no scan kernel and no cleared counters are needed).
+// Out-of-range input turns the sort into a no-op that sets a status bit.
 #include <cmath>
 
 #include "nbreg.h"
@@ -35,11 +40,14 @@
 namespace nb {
 namespace {
 
-constexpr int kSchedThreads = 256;
-constexpr int kSchedRounds = 16;                          // items per thread
-constexpr int kSchedItems = kSchedThreads * kSchedRounds;  // items per work-group
-constexpr int kSchedWaves = kSchedThreads / kWave;
 constexpr int kMaxLevels = 64;
+constexpr int kRounds = 16;   // rounds of 64 items per wave
+// multi-work-group path
+constexpr int kMwThreads = 256;
+constexpr int kMwItems = kMwThreads * kRounds;
+// single-work-group path
+constexpr int kSwThreads = 1024;
+constexpr int kSwItems = kSwThreads * kRounds;
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 {
@@ -47,187 +55,301 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Level of item k, or -1 (with bad set) if the body index or the level is out
-// of range.  src == nullptr: item k is body k.
-__device__ __forceinline__ int32_t item_level(int64_t n, const int32_t *src, int64_t k,
-                                              const int32_t *level, int32_t lmin, int32_t K,
-                                              int32_t &body, bool &bad)
+// Item of round r of this lane: with reff rounds per wave, wave w owns items
+// [w*64*reff, (w+1)*64*reff) of the work-group's range, so item order is
+// (wave, round, lane) order.
+__device__ __forceinline__ int64_t item_index(int64_t base, int r, int reff)
 {
-    const int64_t i = src ? (int64_t)src[k] : k;
-    if (i < 0 || i >= n) {
-        bad = true;
-        return -1;
-    }
-    body = (int32_t)i;
-    const int32_t L = level[i];
-    if (L < lmin || L >= K) {
-        bad = true;
-        return -1;
-    }
-    return L;
+    return base + (int64_t)(threadIdx.x / kWave) * (kWave * reff) + r * kWave +
+           (threadIdx.x & (kWave - 1));
 }
 
-__global__ __launch_bounds__(kSchedThreads) void sched_count_kernel(
-    int64_t n, const int32_t *src, int32_t n_items, const int32_t *level, int32_t lmin,
-    int32_t K, const int32_t *level_end_old, int32_t nblk, int32_t *hist, int32_t *totals,
-    int32_t *flag)
+// Body index (src[k], or k) and level of this lane's items (rounds r < reff);
+// lv = -1 for missing items.  Returns true if an item has a body index outside
+// [0, n) or a level outside [lmin, K).  Loads use clamped indices so all of a
+// kind are in flight together.  copy (optional) receives src[k] per item.
+template <int R>
+__device__ __forceinline__ bool load_items(int64_t n, const int32_t *src, int32_t n_items,
+                                           const int32_t *level, int32_t lmin, int32_t K,
+                                           int64_t base, int reff, int32_t (&body)[R],
+                                           int32_t (&lv)[R], int32_t *copy)
 {
-    __shared__ int32_t h[kMaxLevels];
-    for (int k = threadIdx.x; k < K; k += kSchedThreads) h[k] = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t base = (int64_t)blockIdx.x * kSchedItems;
-    bool bad = false;
-    for (int r = 0; r < kSchedRounds; ++r) {
-        const int64_t k = base + r * kSchedThreads + threadIdx.x;
-        int32_t body = 0;
-        const int32_t L = k < n_items ? item_level(n, src, k, level, lmin, K, body, bad) : -1;
-        uint64_t todo = __ballot(L >= 0);
-        while (todo) {
-            const int first = __builtin_ctzll(todo);
-            const int32_t val = __shfl(L, first);
-            const uint64_t m = __ballot(L == val);
-            if (lane == first) atomicAdd(&h[val], (int32_t)__popcll(m));
-            todo &= ~m;
-        }
-    }
-    // an update's prefix must be exactly the bodies of level >= lmin
-    if (level_end_old && blockIdx.x == 0 && threadIdx.x == 0 && level_end_old[lmin] != n_items)
-        bad = true;
-    if (bad) atomicOr(flag, 1);
-    __syncthreads();
-    for (int k = threadIdx.x; k < K; k += kSchedThreads) {
-        hist[(int64_t)k * nblk + blockIdx.x] = h[k];
-        if (h[k]) atomicAdd(&totals[k], h[k]);
-    }
-}
-
-// One wave per level L = blockIdx.x.
-__global__ __launch_bounds__(kWave) void sched_offsets_kernel(int32_t nblk, int32_t lmin,
-                                                              int32_t K, const int32_t *hist,
-                                                              const int32_t *totals,
-                                                              const int32_t *flag, int32_t *offs,
-                                                              int32_t *level_end,
-                                                              uint32_t *status)
-{
-    const int L = blockIdx.x;
-    const int lane = threadIdx.x;
-    if (*flag) {
-        if (L == 0 && lane == 0 && status) atomicOr(status, (uint32_t)NB_STATUS_BAD_LEVEL);
-        return;
-    }
-    int32_t above = 0;
-    for (int k = L + 1; k < K; ++k) above += totals[k];
-    int32_t run = above;
-    const int32_t *row = hist + (int64_t)L * nblk;
-    for (int32_t b0 = 0; b0 < nblk; b0 += kWave) {
-        const int32_t b = b0 + lane;
-        const int32_t c = b < nblk ? row[b] : 0;
-        int32_t s = c;
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int32_t t = __shfl_up(s, d);
-            if (lane >= d) s += t;
-        }
-        if (b < nblk) offs[(int64_t)L * nblk + b] = run + s - c;
-        run += __shfl(s, kWave - 1);
-    }
-    if (lane == 0) {
-        if (L >= lmin) level_end[L] = above + totals[L];
-        if (L == K - 1) level_end[K] = 0;
-    }
-}
-
-__global__ __launch_bounds__(kSchedThreads) void sched_scatter_kernel(
-    int64_t n, const int32_t *src, int32_t n_items, const int32_t *level, int32_t lmin,
-    int32_t K, int32_t nblk, const int32_t *offs, const int32_t *flag, int32_t *dst)
-{
-    constexpr int kQ = kSchedRounds * kSchedWaves;   // (round, wave) groups, in item order
-    __shared__ int32_t cnt[kQ][kMaxLevels];
-    if (*flag) return;
-    for (int e = threadIdx.x; e < kQ * kMaxLevels; e += kSchedThreads) (&cnt[0][0])[e] = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int64_t base = (int64_t)blockIdx.x * kSchedItems;
-    int32_t lv[kSchedRounds], rk[kSchedRounds], body[kSchedRounds];
+    int32_t raw[R];
 #pragma unroll
-    for (int r = 0; r < kSchedRounds; ++r) {
-        const int64_t k = base + r * kSchedThreads + threadIdx.x;
-        bool bad = false;
-        body[r] = 0;
-        lv[r] = k < n_items ? item_level(n, src, k, level, lmin, K, body[r], bad) : -1;
+    for (int r = 0; r < R; ++r) {
+        body[r] = -1;
+        if (r < reff) {
+            int64_t k = item_index(base, r, reff);
+            k = k < n_items ? k : n_items - 1;
+            body[r] = src ? src[k] : (int32_t)k;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t i = body[r];
+        raw[r] = -1;
+        if (r < reff) raw[r] = level[(i >= 0 && i < n) ? i : 0];
+    }
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t k = item_index(base, r, reff);
+        lv[r] = -1;
+        if (r < reff && k < n_items) {
+            if (copy) copy[k] = body[r];
+            const int32_t i = body[r], L = raw[r];
+            if (i < 0 || i >= n || L < lmin || L >= K)
+                bad = true;
+            else
+                lv[r] = L;
+        }
+    }
+    return bad;
+}
+
+// Ranks within the wave: rk[r] = number of the wave's earlier items with the
+// same level.  Returns the wave's count of level L in lane L (the running
+// counts live in that VGPR and are read back with readlane, so the loop has no
+// memory round trip).
+template <int R>
+__device__ __forceinline__ int32_t wave_rank(const int32_t (&lv)[R], int32_t (&rk)[R])
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    int32_t runv = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
         rk[r] = 0;
         uint64_t todo = __ballot(lv[r] >= 0);
         while (todo) {
             const int first = __builtin_ctzll(todo);
-            const int32_t val = __shfl(lv[r], first);
+            const int32_t val = __builtin_amdgcn_readlane(lv[r], first);
             const uint64_t m = __ballot(lv[r] == val);
-            if (lv[r] == val) rk[r] = (int32_t)lane_rank(m);
-            if (lane == first) cnt[r * kSchedWaves + w][val] = (int32_t)__popcll(m);
+            const int32_t before = __builtin_amdgcn_readlane(runv, val);
+            if (lv[r] == val) rk[r] = before + (int32_t)lane_rank(m);
+            if (lane == val) runv += (int32_t)__popcll(m);
             todo &= ~m;
         }
     }
+    return runv;
+}
+
+// Exclusive scan of the per-wave level counts across the W waves, in wave
+// order, for every level: thread (L = tid / W, w = tid % W) with T = 64 W.
+// Replaces run[w][L] by start[L] + (count of level L in waves < w) and returns
+// the level total in *total (valid in the thread with w == W-1).
+template <int W>
+__device__ __forceinline__ int32_t wave_scan_first(int32_t (*run)[kMaxLevels], int32_t K,
+                                                   int32_t *excl_out)
+{
+    const int L = threadIdx.x / W, w = threadIdx.x % W;
+    const int32_t v = L < K ? run[w][L] : 0;
+    int32_t incl = v;
+    for (int d = 1; d < W; d <<= 1) {
+        const int32_t t = __shfl_up(incl, d, W);
+        if (w >= d) incl += t;
+    }
+    *excl_out = incl - v;
+    return incl;
+}
+
+// above[L] = number of items with level > L from per-level totals tot[]
+// (LDS), computed by wave 0; also writes level_end[L] (L >= lmin) and
+// level_end[K] = 0 when level_end is given.
+__device__ __forceinline__ void level_offsets(const int32_t *tot, int32_t K, int32_t lmin,
+                                              int32_t *above, int32_t *level_end)
+{
+    if (threadIdx.x >= kWave) return;
+    const int lane = threadIdx.x;
+    const int Ll = K - 1 - lane;   // lane l holds level K-1-l
+    const int32_t v = Ll >= 0 ? tot[Ll] : 0;
+    int32_t s = v;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t t = __shfl_up(s, d);
+        if (lane >= d) s += t;
+    }
+    if (Ll >= 0) {
+        above[Ll] = s - v;
+        if (level_end && Ll >= lmin) level_end[Ll] = s;
+    }
+    if (level_end && lane == 0) level_end[K] = 0;
+}
+
+// Whole sort of 1 <= n_items <= kSwItems items in one work-group, written to
+// dst (which may be src).
+__global__ __launch_bounds__(kSwThreads) void sched_single_kernel(
+    int64_t n, const int32_t *src, int32_t n_items, const int32_t *level, int32_t lmin,
+    int32_t K, const int32_t *level_end_old, int32_t *dst, int32_t *level_end,
+    uint32_t *status)
+{
+    constexpr int W = kSwThreads / kWave;
+    __shared__ int32_t run[W][kMaxLevels];
+    __shared__ int32_t tot[kMaxLevels], above[kMaxLevels];
+    __shared__ int32_t bad_any;
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) bad_any = 0;
     __syncthreads();
-    for (int L = threadIdx.x; L < K; L += kSchedThreads) {
-        int32_t run = offs[(int64_t)L * nblk + blockIdx.x];
-        for (int q = 0; q < kQ; ++q) {
-            const int32_t c = cnt[q][L];
-            cnt[q][L] = run;
-            run += c;
+    // spread the items evenly: reff rounds per wave
+    const int reff = (n_items + kSwThreads - 1) / kSwThreads;
+    int32_t body[kRounds], lv[kRounds], rk[kRounds];
+    bool bad = load_items<kRounds>(n, src, n_items, level, lmin, K, 0, reff, body, lv, nullptr);
+    // an update's prefix must be exactly the bodies of level >= lmin
+    if (level_end_old && threadIdx.x == 0 && level_end_old[lmin] != n_items) bad = true;
+    if (bad) atomicOr(&bad_any, 1);
+    run[w][threadIdx.x & (kWave - 1)] = wave_rank<kRounds>(lv, rk);
+    __syncthreads();
+    if (bad_any) {
+        if (threadIdx.x == 0 && status) atomicOr(status, (uint32_t)NB_STATUS_BAD_LEVEL);
+        return;
+    }
+    int32_t excl;
+    const int32_t incl = wave_scan_first<W>(run, K, &excl);
+    const int Ls = threadIdx.x / W, ws = threadIdx.x % W;
+    if (Ls < K && ws == W - 1) tot[Ls] = incl;
+    __syncthreads();
+    level_offsets(tot, K, lmin, above, level_end);
+    __syncthreads();
+    if (Ls < K) run[ws][Ls] = above[Ls] + excl;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r)
+        if (lv[r] >= 0) dst[run[w][lv[r]] + rk[r]] = body[r];
+}
+
+// Multi-work-group pass 1: per-block level counts into hist[L][b], the block's
+// range flag into bad_blk[b], and (update) the prefix copied to copy[].
+__global__ __launch_bounds__(kMwThreads) void sched_count_kernel(
+    int64_t n, const int32_t *src, int32_t n_items, const int32_t *level, int32_t lmin,
+    int32_t K, const int32_t *level_end_old, int32_t nblk, int32_t *hist, int32_t *bad_blk,
+    int32_t *copy)
+{
+    __shared__ int32_t h[kMaxLevels];
+    __shared__ int32_t bad_any;
+    if (threadIdx.x < kMaxLevels) h[threadIdx.x] = 0;
+    if (threadIdx.x == 0) bad_any = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    int32_t body[kRounds], lv[kRounds];
+    bool bad = load_items<kRounds>(n, src, n_items, level, lmin, K,
+                                   (int64_t)blockIdx.x * kMwItems, kRounds, body, lv, copy);
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        uint64_t todo = __ballot(lv[r] >= 0);
+        while (todo) {
+            const int first = __builtin_ctzll(todo);
+            const int32_t val = __builtin_amdgcn_readlane(lv[r], first);
+            const uint64_t m = __ballot(lv[r] == val);
+            if (lane == first) atomicAdd(&h[val], (int32_t)__popcll(m));
+            todo &= ~m;
+        }
+    }
+    if (level_end_old && blockIdx.x == 0 && threadIdx.x == 0 && level_end_old[lmin] != n_items)
+        bad = true;
+    if (bad) atomicOr(&bad_any, 1);
+    __syncthreads();
+    if (threadIdx.x < K) hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x == 0) bad_blk[blockIdx.x] = bad_any;
+}
+
+// Multi-work-group pass 2: offsets of this block from the count rows, then the
+// scatter.  Block 0 writes level_end and the status bit.
+__global__ __launch_bounds__(kMwThreads) void sched_scatter_kernel(
+    int64_t n, const int32_t *src, int32_t n_items, const int32_t *level, int32_t lmin,
+    int32_t K, int32_t nblk, const int32_t *hist, const int32_t *bad_blk, int32_t *dst,
+    int32_t *level_end, uint32_t *status)
+{
+    constexpr int W = kMwThreads / kWave;   // 4 threads per level slot below
+    __shared__ int32_t run[W][kMaxLevels];
+    __shared__ int32_t tot[kMaxLevels], above[kMaxLevels], before[kMaxLevels];
+    int bad = 0;
+    for (int32_t b = threadIdx.x; b < nblk; b += kMwThreads) bad |= bad_blk[b];
+    if (__syncthreads_or(bad)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && status)
+            atomicOr(status, (uint32_t)NB_STATUS_BAD_LEVEL);
+        return;
+    }
+    const int w = threadIdx.x / kWave;
+    {
+        // level totals and the counts of blocks before this one: thread
+        // (L = tid / W, part = tid % W) sums a quarter of row L
+        const int L = threadIdx.x / W, part = threadIdx.x % W;
+        int32_t all = 0, bef = 0;
+        if (L < K) {
+            const int32_t *row = hist + (int64_t)L * nblk;
+            for (int32_t b = part; b < nblk; b += W) {
+                const int32_t c = row[b];
+                all += c;
+                bef += b < (int32_t)blockIdx.x ? c : 0;
+            }
+        }
+        for (int d = 1; d < W; d <<= 1) {
+            all += __shfl_xor(all, d, W);
+            bef += __shfl_xor(bef, d, W);
+        }
+        if (L < K && part == 0) {
+            tot[L] = all;
+            before[L] = bef;
         }
     }
     __syncthreads();
+    level_offsets(tot, K, lmin, above, blockIdx.x == 0 ? level_end : nullptr);
+    int32_t body[kRounds], lv[kRounds], rk[kRounds];
+    (void)load_items<kRounds>(n, src, n_items, level, lmin, K, (int64_t)blockIdx.x * kMwItems,
+                              kRounds, body, lv, nullptr);
+    run[w][threadIdx.x & (kWave - 1)] = wave_rank<kRounds>(lv, rk);
+    __syncthreads();
+    int32_t excl;
+    (void)wave_scan_first<W>(run, K, &excl);
+    const int Ls = threadIdx.x / W, ws = threadIdx.x % W;
+    __syncthreads();
+    if (Ls < K) run[ws][Ls] = above[Ls] + before[Ls] + excl;
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSchedRounds; ++r)
-        if (lv[r] >= 0) dst[cnt[r * kSchedWaves + w][lv[r]] + rk[r]] = body[r];
-}
-
-__global__ __launch_bounds__(256) void sched_copy_kernel(const int32_t *flag, const int32_t *tmp,
-                                                         int32_t n_items, int32_t *order)
-{
-    if (*flag) return;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_items;
-         k += (int64_t)gridDim.x * blockDim.x)
-        order[k] = tmp[k];
+    for (int r = 0; r < kRounds; ++r)
+        if (lv[r] >= 0) dst[run[w][lv[r]] + rk[r]] = body[r];
 }
 
 struct SchedScratch {
-    int32_t *hist, *offs, *totals, *flag, *tmp;
+    int32_t *hist, *bad_blk, *copy;
 };
 
-// Scratch: hist and offs [K][nblk], totals [64] + flag (cleared together),
-// and (update) the re-sorted prefix.
-int sched_scratch(nb_ctx *ctx, int32_t nblk, int32_t K, int32_t n_tmp, SchedScratch &s)
+// Scratch of the multi-work-group path: hist [K][nblk], bad_blk [nblk] and
+// (update) a copy of the prefix.
+int sched_prepare(nb_ctx *ctx, int32_t n_items, int32_t K, bool in_place, SchedScratch &s)
 {
+    s = SchedScratch{};
+    if (n_items <= kSwItems) return NB_OK;
+    const int32_t nblk = (n_items + kMwItems - 1) / kMwItems;
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t grid = up(sizeof(int32_t) * (size_t)nblk * K);
-    const size_t small = up(sizeof(int32_t) * (kMaxLevels + 64));
-    const size_t bytes = 2 * grid + small + up(sizeof(int32_t) * (size_t)n_tmp);
-    const int rc = nbrt::ensure_scratch(ctx, bytes);
+    const size_t h = up(sizeof(int32_t) * (size_t)nblk * K);
+    const size_t f = up(sizeof(int32_t) * (size_t)nblk);
+    const size_t c = in_place ? up(sizeof(int32_t) * (size_t)n_items) : 0;
+    const int rc = nbrt::ensure_scratch(ctx, h + f + c);
     if (rc != NB_OK) return rc;
     char *p = (char *)ctx->scratch;
     s.hist = (int32_t *)p;
-    s.offs = (int32_t *)(p + grid);
-    s.totals = (int32_t *)(p + 2 * grid);
-    s.flag = s.totals + kMaxLevels;
-    s.tmp = (int32_t *)(p + 2 * grid + small);
+    s.bad_blk = (int32_t *)(p + h);
+    s.copy = in_place ? (int32_t *)(p + h + f) : nullptr;
     return NB_OK;
 }
 
-// Counting sort of n_items items (body src[k], or k) by level into dst.
+// Counting sort of n_items items (body src[k], or k) by level into dst (dst
+// may be src; then the multi-work-group path reads the copy made by pass 1).
 hipError_t sched_sort(nb_ctx *ctx, int64_t n, const int32_t *src, int32_t n_items,
                       const int32_t *level, int32_t lmin, int32_t K, const int32_t *check_le,
-                      const SchedScratch &s, int32_t nblk, int32_t *dst, int32_t *level_end,
-                      uint32_t *status)
+                      const SchedScratch &s, int32_t *dst, int32_t *level_end, uint32_t *status)
 {
-    hipError_t e = launch_fill_i32(s.totals, 0, kMaxLevels + 64, ctx->stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sched_count_kernel, dim3((unsigned)nblk), dim3(kSchedThreads), 0,
+    if (n_items <= kSwItems) {
+        hipLaunchKernelGGL(sched_single_kernel, dim3(1), dim3(kSwThreads), 0, ctx->stream, n,
+                           src, n_items, level, lmin, K, check_le, dst, level_end, status);
+        return hipGetLastError();
+    }
+    const int32_t nblk = (n_items + kMwItems - 1) / kMwItems;
+    hipLaunchKernelGGL(sched_count_kernel, dim3((unsigned)nblk), dim3(kMwThreads), 0,
                        ctx->stream, n, src, n_items, level, lmin, K, check_le, nblk, s.hist,
-                       s.totals, s.flag);
-    hipLaunchKernelGGL(sched_offsets_kernel, dim3((unsigned)K), dim3(kWave), 0, ctx->stream,
-                       nblk, lmin, K, s.hist, s.totals, s.flag, s.offs, level_end, status);
-    hipLaunchKernelGGL(sched_scatter_kernel, dim3((unsigned)nblk), dim3(kSchedThreads), 0,
-                       ctx->stream, n, src, n_items, level, lmin, K, nblk, s.offs, s.flag, dst);
+                       s.bad_blk, s.copy);
+    hipLaunchKernelGGL(sched_scatter_kernel, dim3((unsigned)nblk), dim3(kMwThreads), 0,
+                       ctx->stream, n, s.copy ? s.copy : src, n_items, level, lmin, K, nblk,
+                       s.hist, s.bad_blk, dst, level_end, status);
     return hipGetLastError();
 }
 
@@ -246,14 +368,13 @@ int nb_sched_build(nb_ctx *ctx, int64_t n, const int32_t *level, int32_t k_max, 
         return NB_ERR_INVALID_ARG;
     if (!ctx->usable) return NB_ERR_UNSUPPORTED;
     const int32_t K = k_max + 1;
-    const int32_t nblk = (int32_t)((n + nb::kSchedItems - 1) / nb::kSchedItems);
     nb::SchedScratch s;
-    int rc = nb::sched_scratch(ctx, nblk, K, 0, s);
+    int rc = nb::sched_prepare(ctx, (int32_t)n, K, false, s);
     if (rc != NB_OK) return rc;
     hipEvent_t ev[2];
     hipError_t e = timed_begin(ctx, NB_CLASS_SCHED, ev);
     if (e == hipSuccess)
-        e = nb::sched_sort(ctx, n, nullptr, (int32_t)n, level, 0, K, nullptr, s, nblk, order,
+        e = nb::sched_sort(ctx, n, nullptr, (int32_t)n, level, 0, K, nullptr, s, order,
                            level_end, status);
     if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_SCHED, ev);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
@@ -268,21 +389,14 @@ int nb_sched_update(nb_ctx *ctx, int64_t n, int32_t n_active, int32_t L, const i
     if (!ctx->usable) return NB_ERR_UNSUPPORTED;
     if (n_active == 0) return NB_OK;
     const int32_t K = k_max + 1;
-    const int32_t nblk = (n_active + nb::kSchedItems - 1) / nb::kSchedItems;
     nb::SchedScratch s;
-    int rc = nb::sched_scratch(ctx, nblk, K, n_active, s);
+    int rc = nb::sched_prepare(ctx, n_active, K, true, s);
     if (rc != NB_OK) return rc;
     hipEvent_t ev[2];
     hipError_t e = timed_begin(ctx, NB_CLASS_SCHED, ev);
     if (e == hipSuccess)
-        e = nb::sched_sort(ctx, n, order, n_active, level, L, K, level_end, s, nblk, s.tmp,
+        e = nb::sched_sort(ctx, n, order, n_active, level, L, K, level_end, s, order,
                            level_end, status);
-    if (e == hipSuccess) {
-        const unsigned g = (unsigned)std::min<int64_t>(1024, (n_active + 255) / 256);
-        hipLaunchKernelGGL(nb::sched_copy_kernel, dim3(g), dim3(256), 0, ctx->stream, s.flag,
-                           s.tmp, n_active, order);
-        e = hipGetLastError();
-    }
     if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_SCHED, ev);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
 }

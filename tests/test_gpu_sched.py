@@ -44,7 +44,7 @@ def _segments_match(order, le, lev, k_max):
 
 
 @pytest.mark.parametrize("n,k_max", [(1, 0), (1000, 5), (4095, 20), (4096, 20), (4097, 20),
-                                     (300001, 22), (1 << 20, 63)])
+                                     (8192, 20), (16384, 20), (16385, 20), (300001, 22), (1 << 20, 63)])
 def test_build_bitwise(ctx, n, k_max):
     say(f"sched build n={n} k_max={k_max}")
     lev = _levels(900 + n, n, k_max)
@@ -124,15 +124,18 @@ def test_block_step_sequence(ctx, n, k_lo, k_max, steps):
     assert max(sizes) > 4096 or n < 4096
 
 
-def test_update_rejects_bad_input(ctx):
+@pytest.mark.parametrize("L", [5, 8])
+def test_update_rejects_bad_input(ctx, L):
+    """Both the one-work-group path (block <= 16384) and the multi-work-group
+    path leave the list untouched on bad input."""
     n, k_max = 20000, 12
     rng = np.random.default_rng(977)
     lev = W.sample_levels(rng, n, 3, k_max, k_peak=6)
     g_lev = dev(lev)
     order, le = nb.sched_build(g_lev, k_max, ctx=ctx)
     o0, l0 = host(order), host(le)
-    L = 5
     n_a = int(l0[L])
+    assert (n_a > 16384) == (L == 5), n_a
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     # a new level coarser than the block level
     bad = g_lev.clone()
