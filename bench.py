@@ -72,6 +72,59 @@ def measured_traffic(prec: str):
     return d.get(prec, {}).get("hbm_bytes_per_launch")
 
 
+def sched_leg(nb, W, s, ctx, dev, reps=20):
+    """Sorting-list scheduler (section 3.3.1) on the cluster's step levels:
+    full build, then the O(N_i) update of each level's block, weighted by how
+    often each level is due in one 2^-3 cycle of the hierarchy."""
+    import torch
+    n = s["n"]
+    k_max = 20
+    lev_h = s["levels"].astype(np.int32)
+    lev_d = dev(lev_h)
+    order_d, le_d = nb.sched_build(lev_d, k_max, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.reset_timing()
+    ctx.enable_timing(True)
+    c1 = time.perf_counter()
+    for _ in range(10):
+        nb.sched_build(lev_d, k_max, order=order_d, level_end=le_d, ctx=ctx)
+    torch.cuda.synchronize()
+    b_wall = (time.perf_counter() - c1) * 1e6 / 10
+    bms, bl = ctx.kernel_time(nb.CLASS_SCHED)
+    b_us = bms * 1e3 / max(bl, 1)
+    le_h = le_d.cpu().numpy()
+    per_level, cyc_us, cyc_bodies = {}, 0.0, 0
+    for L in range(3, k_max + 1):
+        n_a = int(le_h[L])
+        if n_a == 0:
+            continue
+        ctx.reset_timing()
+        c1 = time.perf_counter()
+        for _ in range(reps):
+            nb.sched_update(order_d, le_d, n_a, L, lev_d, k_max, ctx=ctx)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - c1) * 1e6 / reps
+        ums, ul = ctx.kernel_time(nb.CLASS_SCHED)
+        us = ums * 1e3 / max(ul, 1)
+        per_level[str(L)] = {"n_active": n_a, "update_us": round(us, 2),
+                             "wall_us": round(wall, 2),
+                             "GB_per_s": round(28.0 * n_a / us * 1e-3, 1)}
+        cyc_us += W.level_weight(L) * us
+        cyc_bodies += W.level_weight(L) * n_a
+    ctx.enable_timing(False)
+    blocks = sum(W.level_weight(L) for L in range(3, k_max + 1) if str(L) in per_level)
+    log(f"sched: build {b_us:.1f} us, cycle of {blocks} blocks: update "
+        f"{cyc_us * 1e-3:.2f} ms ({cyc_us / max(blocks, 1):.1f} us/block)")
+    return {
+        "workload": f"N={n} step levels 3..20 of the same cluster, k_max {k_max}",
+        "build_us": round(b_us, 2), "build_wall_us": round(b_wall, 2),
+        "build_GB_per_s": round(12.0 * n / b_us * 1e-3, 1),
+        "update_per_level": per_level,
+        "cycle": {"blocks": blocks, "active_bodies": cyc_bodies,
+                  "update_ms": round(cyc_us * 1e-3, 3),
+                  "mean_update_us": round(cyc_us / max(blocks, 1), 2)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +135,9 @@ def main():
                     help="rows of the full block timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-levels", action="store_true")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--sched-only", action="store_true",
+                    help="only time the block-step scheduler on the same cluster's levels "
+                         "and print its figures (used for kernel profiles)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (FP64 elementwise kernel) "
                          "and print its bandwidth; used to scale rocprofv3 byte counters")
@@ -131,6 +187,9 @@ def main():
            torch.empty((n_i, cap), dtype=torch.int32, device="cuda"),
            torch.empty(1, dtype=torch.int32, device="cuda"))
     ctx = nb.Context(0)
+    if args.sched_only:
+        print(json.dumps({"sched": sched_leg(nb, W, s, ctx, dev)}), flush=True)
+        return
 
     def step(prec):
         nb.predict(x, v, a, jk, t0d, t, out=(xp, vp), ctx=ctx)
@@ -265,56 +324,8 @@ def main():
             log(f"batched {prec}: {ms:.2f} ms, {pairs4 / ms * 1e-6:.1f} G pairs/s")
             del o4
 
-    # sorting-list scheduler (section 3.3.1) on the same cluster's step levels:
-    # full build, then the O(N_i) update of each level's block, weighted by how
-    # often each level is due in one 2^-3 cycle of the hierarchy
     if not args.no_levels:
-        k_max = 20
-        lev_h = s["levels"].astype(np.int32)
-        lev_d = dev(lev_h)
-        order_d, le_d = nb.sched_build(lev_d, k_max, ctx=ctx)
-        torch.cuda.synchronize()
-        ctx.reset_timing()
-        ctx.enable_timing(True)
-        c1 = time.perf_counter()
-        for _ in range(10):
-            nb.sched_build(lev_d, k_max, order=order_d, level_end=le_d, ctx=ctx)
-        torch.cuda.synchronize()
-        b_wall = (time.perf_counter() - c1) * 1e6 / 10
-        bms, bl = ctx.kernel_time(nb.CLASS_SCHED)
-        b_us = bms * 1e3 / max(bl, 1)
-        le_h = le_d.cpu().numpy()
-        per_level, cyc_us, cyc_bodies = {}, 0.0, 0
-        for L in range(3, k_max + 1):
-            n_a = int(le_h[L])
-            if n_a == 0:
-                continue
-            ctx.reset_timing()
-            reps = 20
-            c1 = time.perf_counter()
-            for _ in range(reps):
-                nb.sched_update(order_d, le_d, n_a, L, lev_d, k_max, ctx=ctx)
-            torch.cuda.synchronize()
-            wall = (time.perf_counter() - c1) * 1e6 / reps
-            ums, ul = ctx.kernel_time(nb.CLASS_SCHED)
-            us = ums * 1e3 / max(ul, 1)
-            per_level[str(L)] = {"n_active": n_a, "update_us": round(us, 2),
-                                 "wall_us": round(wall, 2),
-                                 "GB_per_s": round(28.0 * n_a / us * 1e-3, 1)}
-            cyc_us += W.level_weight(L) * us
-            cyc_bodies += W.level_weight(L) * n_a
-        ctx.enable_timing(False)
-        blocks = sum(W.level_weight(L) for L in range(3, k_max + 1) if str(L) in per_level)
-        extras["sched"] = {
-            "workload": f"N={n} step levels 3..20 of the same cluster, k_max {k_max}",
-            "build_us": round(b_us, 2), "build_wall_us": round(b_wall, 2),
-            "build_GB_per_s": round(12.0 * n / b_us * 1e-3, 1),
-            "update_per_level": per_level,
-            "cycle": {"blocks": blocks, "active_bodies": cyc_bodies,
-                      "update_ms": round(cyc_us * 1e-3, 3),
-                      "mean_update_us": round(cyc_us / max(blocks, 1), 2)}}
-        log(f"sched: build {b_us:.1f} us, cycle of {blocks} blocks: update "
-            f"{cyc_us * 1e-3:.2f} ms ({cyc_us / max(blocks, 1):.1f} us/block)")
+        extras["sched"] = sched_leg(nb, W, s, ctx, dev)
 
     # CPU oracle on a bounded sample of the same full block
     cpu = None
