@@ -21,6 +21,9 @@ Parity status per function (what pins it; see tests/test_oracle_pins.py):
   sched.*          -- sorting-list selection of active bodies (oracle/sched.py):
                       hand-worked golden list, pairwise order, exact rational
                       block-step simulation (pinned)
+  radius.*         -- neighbour-radius control toward NNBOPT (oracle/radius.py):
+                      Decimal cube roots, clamp and fixed-point cases, uniform-
+                      density counts, fit-loop invariants (pinned)
 """
 from __future__ import annotations
 

@@ -482,3 +482,92 @@ def test_block_step_selection_exact_rational():
         t_now = T
     assert S.due_level(1.0, 8) == 0 and S.due_level(0.375, 8) == 3
     assert S.due_level(0.5, 8) == 1 and S.due_level(2.0 ** -9, 8) == -1
+
+
+# --------------------------------------------------------------------------- #
+# neighbour-radius control (Table A1, NNBOPT; uniform-density reading)
+# --------------------------------------------------------------------------- #
+def _ulp(x):
+    return np.spacing(np.abs(x))
+
+
+def test_pow23_against_decimal_cube_roots():
+    """q^(2/3) by the fixed Newton steps is within 2 ulp of the 50-digit
+    cube root of q*q, and exact where the root is a representable value."""
+    import oracle.radius as R
+    getcontext().prec = 50
+    rng = np.random.default_rng(801)
+    q = np.concatenate([np.exp(rng.uniform(np.log(1e-4), np.log(1e4), 4000)),
+                        [1.0, 2.0, 0.5, 3.0, 64.0 / 63.0, 63.0 / 64.0, 1e-6, 1e6]])
+    y = R.pow23(q)
+    for qi, yi in zip(q.tolist(), y.tolist()):
+        ex = (Decimal(qi) * Decimal(qi)) ** (Decimal(1) / Decimal(3))
+        assert abs(Decimal(yi) - ex) <= 2 * Decimal(float(np.spacing(yi))), (qi, yi)
+    for qi, exact in ((8.0, 4.0), (1.0, 1.0), (0.125, 0.25), (27.0, 9.0), (1 / 64, 1 / 16)):
+        assert R.pow23(np.array([qi]))[0] == exact
+
+
+def test_radius_update_rules():
+    import oracle.radius as R
+    rs2 = np.array([0.01, 0.02, 0.04, 0.0, -1.0, 0.03, 0.05])
+    cnt = np.array([64, 512, 8, 10, 10, 0, 1], np.int64)
+    out = R.radius_update(rs2, cnt, 64, 0.5, 2.0)
+    assert out[0] == 0.01                      # at target: unchanged, bit for bit
+    assert out[1] == 0.02 * 0.5                # (1/8)^(2/3) = 1/4, clamped to 0.5
+    assert out[2] == 0.04 * 2.0                # 8^(2/3) = 4, clamped to 2
+    assert out[3] == 0.0 and out[4] == -1.0    # no radius: kept
+    assert out[5] == 0.03 * 2.0 and out[6] == 0.05 * 2.0   # empty sphere counts as one
+    wide = R.radius_update(np.array([0.01, 0.01, 0.01]), np.array([512, 0, 1]), 64, 0.01, 100.0)
+    assert wide[0] == 0.01 * 0.25 and wide[1] == wide[2] == 0.01 * 16.0
+    # the shrink of an overflowed row never grows it and never cuts below 1/4
+    s = R.overflow_shrink(np.full(5, 0.08), np.array([65, 100, 512, 4096, 10 ** 6]), 64)
+    assert (s < 0.08).all() and (s >= 0.02).all()
+    assert s[2] == 0.08 * 0.25 and s[4] == 0.02
+
+
+def test_radius_update_reaches_target_in_uniform_density():
+    """Uniform random bodies: from radii holding a wide spread of counts, one
+    unclamped update brings the mean count of interior rows to NNBOPT within
+    the Poisson scatter (counts by a KD-tree, independent of the oracle)."""
+    from scipy.spatial import cKDTree
+    import oracle.radius as R
+    rng = np.random.default_rng(805)
+    n, nnbopt = 200000, 64
+    x = rng.random((n, 3))
+    tree = cKDTree(x)
+    rows = np.nonzero((np.abs(x - 0.5) < 0.3).all(axis=1))[0][:3000]
+    r0 = np.exp(rng.uniform(np.log(0.008), np.log(0.03), rows.size))
+    c0 = np.array([len(v) - 1 for v in tree.query_ball_point(x[rows], r0)])
+    ok = c0 > 4
+    rs2 = R.radius_update(r0[ok] ** 2, c0[ok], nnbopt, 1e-6, 1e6)
+    c1 = np.array([len(v) - 1 for v in tree.query_ball_point(x[rows[ok]], np.sqrt(rs2))])
+    assert abs(c1.mean() / nnbopt - 1) < 0.04, c1.mean()
+    assert np.median(np.abs(c0[ok] / nnbopt - 1)) > 0.5      # the start was far off
+    assert np.median(np.abs(c1 / nnbopt - 1)) < 0.2
+
+
+def test_regular_fit_invariants():
+    """Overflowed rows are shrunk and recomputed until none overflows; rows
+    that never overflowed keep radius and results; the final block equals a
+    direct regular-force call with the final radii."""
+    import oracle.radius as R
+    s = W.small_state(811, 2000, k_nn=40)
+    blk = np.arange(0, 2000, 3, dtype=np.int32)
+    rs2 = s["rs2"][blk]
+    c_true = oracle.regular(s["x"], s["v"], s["m"], blk, rs2, 400)[2]
+    cap = int(np.percentile(c_true, 60))
+    a0, j0, c0, l0, ovf0, _ = oracle.regular(s["x"], s["v"], s["m"], blk, rs2, cap)
+    assert ovf0 == 1 and (c0 > cap).sum() > 100 and (c0 == cap).sum() > 5
+    acc, jerk, cnt, lst, ovf, rs2f, rounds = R.regular_fit(s["x"], s["v"], s["m"], blk, rs2,
+                                                            cap, cap - 4, 8)
+    assert ovf == 0 and rounds >= 1 and (cnt <= cap).all()
+    keep = c0 <= cap
+    assert np.array_equal(rs2f[keep], rs2[keep])
+    assert (rs2f[~keep] < rs2[~keep]).all()
+    assert np.array_equal(acc[:, keep], a0[:, keep]) and np.array_equal(cnt[keep], c0[keep])
+    d = oracle.regular(s["x"], s["v"], s["m"], blk, rs2f, cap)
+    for got, ref in zip((acc, jerk, cnt, lst), d[:4]):
+        assert np.array_equal(got, ref)
+    # a round limit of 0 leaves the overflowing result as is
+    r0 = R.regular_fit(s["x"], s["v"], s["m"], blk, rs2, cap, cap - 4, 0)
+    assert r0[4] == 1 and r0[6] == 0 and np.array_equal(r0[5], rs2)
