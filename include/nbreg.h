@@ -98,7 +98,8 @@ int nb_ctx_set_scratch_limit(nb_ctx *ctx, int64_t bytes);
  * launch count of one kernel class since the last reset (class 0 = regular
  * force main kernel, 1 = cross-split reduce, 2 = predictor, 3 = adjoint,
  * 4 = batched, 5 = mixed-precision FP64 refinement, 6 = irregular force
- * and potential, 7 = block-step scheduler). */
+ * and potential, 7 = block-step scheduler, 8 = radius control: update,
+ * compaction and scatter; the recomputed rows count under 0, 1, 5). */
 int nb_ctx_enable_timing(nb_ctx *ctx, int on);
 int nb_ctx_kernel_time(nb_ctx *ctx, int kernel_class, double *ms, int64_t *launches);
 int nb_ctx_reset_timing(nb_ctx *ctx);
@@ -231,6 +232,43 @@ int nb_hermite_correct(nb_ctx *ctx, int64_t n, const double *h, const double *x0
  * double) = 1/2 sum_i m_i phi_i, reduced in a fixed order. */
 int nb_potential(nb_ctx *ctx, int64_t n, const double *x, const double *m, double *phi,
                  double *energy);
+
+/* ---- neighbour-radius control (Table A1: neighbour number toward NNBOPT) -- */
+
+/* The paper steers each body's neighbour number toward the input parameter
+ * NNBOPT.  Rule used here (uniform density: the count grows as the sphere's
+ * volume): rs2 is scaled by f = (target / count)^(2/3), where the 2/3 power is
+ * computed as the cube root of q*q by eight Newton steps
+ *   y <- y - (y*y*y - x) / (3*y*y)   (as t = y*y; y - (t*y - x) / (3*t))
+ * from y = 2^floor(e/3), q*q = frac * 2^e with frac in [0.5, 1), in IEEE FP64
+ * without contraction, so results are reproducible bit for bit.
+ *
+ * nb_radius_update: next-step squared radii of a block, row by row:
+ *   rs2_new[b] = rs2[b] * min(max(f, f_min), f_max),  target = nnbopt,
+ *   count = max(nb_count[b], 1);  rows with rs2[b] <= 0 are copied unchanged.
+ * nb_count, rs2, rs2_new: [n_i] device arrays; rs2_new may alias rs2.
+ * Errors: n_i < 0, nnbopt < 1, f_min <= 0, f_max < f_min or not finite, NULL
+ * arrays with n_i > 0. */
+int nb_radius_update(nb_ctx *ctx, int32_t n_i, const int32_t *nb_count, const double *rs2,
+                     int32_t nnbopt, double f_min, double f_max, double *rs2_new);
+
+/* nb_regular_force_fit: nb_regular_force, then up to max_rounds rounds of:
+ * every row with nb_count > nb_cap gets rs2[b] *= min(max(f, 1/4), 1) with
+ * target = min(nnbopt, nb_cap), and those rows alone are recomputed with the
+ * new radii (their acc, jerk, count and list replace the old ones).  rs2 is
+ * IN/OUT: the caller's array holds the final radii.  Rounds stop when no row
+ * overflows; *overflow reports the final state.  Each round synchronises the
+ * stream twice (to read the overflow word and the number of rows).
+ * rounds_host (optional, host) receives the number of rounds made.  Rows are
+ * recomputed in ascending row order, so results are deterministic and a row's
+ * result equals a plain nb_regular_force call with its final radius.
+ * Arguments and outputs as nb_regular_force, plus: nb_cap >= 1, nnbopt >= 1,
+ * max_rounds >= 0 (0: plain nb_regular_force). */
+int nb_regular_force_fit(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                         const double *m, int32_t n_i, const int32_t *i_block, double *rs2,
+                         int32_t nb_cap, nb_precision prec, int32_t nnbopt, int32_t max_rounds,
+                         double *acc, double *jerk, int32_t *nb_count, int32_t *nb_list,
+                         int32_t *overflow, uint32_t *status, int32_t *rounds_host);
 
 /* ---- block-step scheduler: the sorting list (section 3.3.1) ------------- */
 

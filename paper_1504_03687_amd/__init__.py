@@ -26,14 +26,14 @@ __all__ = [
     "NbError", "Context", "lib", "library_path", "context", "predict", "regular_force",
     "regular_force_adjoint", "regular_force_batched", "autotune", "RegularForce",
     "irregular_force", "hermite_correct", "potential", "sched_build", "sched_update",
-    "sched_next", "FP64", "MIXED", "STATUS_OVERFLOW", "STATUS_BAD_INDEX",
+    "sched_next", "radius_update", "regular_force_fit", "FP64", "MIXED", "STATUS_OVERFLOW", "STATUS_BAD_INDEX",
     "STATUS_NONFINITE", "STATUS_BAD_LEVEL",
 ]
 
 FP64, MIXED = 0, 1
 STATUS_OVERFLOW, STATUS_BAD_INDEX, STATUS_NONFINITE, STATUS_BAD_LEVEL = 1, 2, 4, 8
 (CLASS_FORCE, CLASS_MERGE, CLASS_PREDICT, CLASS_ADJOINT, CLASS_BATCHED, CLASS_REDO,
- CLASS_STEP, CLASS_SCHED) = range(8)
+ CLASS_STEP, CLASS_SCHED, CLASS_RADIUS) = range(9)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # NBREG_LIBRARY may point at another build of the same library (e.g. a
@@ -98,6 +98,9 @@ def lib() -> C.CDLL:
             "nb_sched_update": ([vp, i64, i32, i32, vp, i32, vp, vp, u32p], C.c_int),
             "nb_sched_next": ([dbl, i32, vp, C.POINTER(dbl), C.POINTER(i32),
                                C.POINTER(i32)], C.c_int),
+            "nb_radius_update": ([vp, i32, vp, vp, i32, dbl, dbl, vp], C.c_int),
+            "nb_regular_force_fit": ([vp, i64, vp, vp, vp, i32, vp, vp, i32, C.c_int, i32, i32,
+                                      vp, vp, vp, vp, vp, u32p, C.POINTER(i32)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -455,6 +458,52 @@ def sched_next(t_now: float, k_max: int, level_end_host):
     _check(lib().nb_sched_next(float(t_now), int(k_max), C.cast(le, C.c_void_p),
                                C.byref(t_new), C.byref(L), C.byref(n_a)), "nb_sched_next")
     return t_new.value, L.value, n_a.value
+
+
+def radius_update(nb_count, rs2, nnbopt: int, f_min: float = 0.5, f_max: float = 2.0,
+                  out=None, ctx: Context | None = None):
+    """Next-step squared neighbour radii toward nnbopt neighbours (see
+    nb_radius_update); returns rs2_new (may be rs2 itself via out=rs2)."""
+    n_i = rs2.shape[0]
+    _dev(rs2, "rs2", torch.float64, (n_i,))
+    _dev(nb_count, "nb_count", torch.int32, (n_i,))
+    out = torch.empty_like(rs2) if out is None else _dev(out, "out", torch.float64, (n_i,))
+    ctx = ctx or context(rs2.device.index)
+    ctx._bind_stream()
+    _check(lib().nb_radius_update(ctx.handle, n_i, _ptr(nb_count), _ptr(rs2), int(nnbopt),
+                                  float(f_min), float(f_max), _ptr(out)), "nb_radius_update")
+    return out
+
+
+def regular_force_fit(xp, vp, m, i_block, rs2, nb_cap: int, nnbopt: int, max_rounds: int = 8,
+                      precision="fp64", status=None, ctx: Context | None = None):
+    """Regular force with overflowed rows shrunk toward min(nnbopt, nb_cap)
+    neighbours and recomputed (see nb_regular_force_fit).  rs2 is updated in
+    place.  Returns (acc, jerk, nb_count, nb_list, overflow, rounds)."""
+    n = m.shape[0]
+    n_i = i_block.shape[0]
+    _dev(xp, "xp", torch.float64, (3, n))
+    _dev(vp, "vp", torch.float64, (3, n))
+    _dev(m, "m", torch.float64, (n,))
+    _dev(i_block, "i_block", torch.int32, (n_i,))
+    _dev(rs2, "rs2", torch.float64, (n_i,))
+    if status is not None:
+        _dev(status, "status", torch.int32, (1,))
+    dv = xp.device
+    acc = torch.empty((3, n_i), dtype=torch.float64, device=dv)
+    jerk = torch.empty_like(acc)
+    cnt = torch.empty(n_i, dtype=torch.int32, device=dv)
+    lst = torch.empty((n_i, nb_cap), dtype=torch.int32, device=dv)
+    ovf = torch.empty(1, dtype=torch.int32, device=dv)
+    rounds = C.c_int32(0)
+    ctx = ctx or context(dv.index)
+    ctx._bind_stream()
+    _check(lib().nb_regular_force_fit(ctx.handle, n, _ptr(xp), _ptr(vp), _ptr(m), n_i,
+                                      _ptr(i_block), _ptr(rs2), int(nb_cap), _prec(precision),
+                                      int(nnbopt), int(max_rounds), _ptr(acc), _ptr(jerk),
+                                      _ptr(cnt), _ptr(lst), _ptr(ovf), _ptr(status),
+                                      C.byref(rounds)), "nb_regular_force_fit")
+    return acc, jerk, cnt, lst, ovf, rounds.value
 
 
 class RegularForce(torch.autograd.Function):

@@ -21,7 +21,8 @@ enum {
     NB_CLASS_REDO = 5,
     NB_CLASS_STEP = 6,
     NB_CLASS_SCHED = 7,
-    NB_NCLASS = 8
+    NB_CLASS_RADIUS = 8,
+    NB_NCLASS = 9
 };
 
 namespace nbrt {
@@ -43,6 +44,10 @@ struct nb_ctx {
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     size_t scratch_limit = 0;
+    // second buffer for entry points that call other entry points (which
+    // use 'scratch') while holding data of their own
+    void *aux = nullptr;
+    size_t aux_bytes = 0;
     // plan control
     nb::Plan forced{};
     bool has_forced = false;
@@ -66,6 +71,7 @@ struct nb_ctx {
 namespace nbrt {
 int hip_fail(nb_ctx *ctx, hipError_t e);
 int ensure_scratch(nb_ctx *ctx, size_t bytes);
+int ensure_aux(nb_ctx *ctx, size_t bytes);
 hipError_t timed_begin(nb_ctx *ctx, int cls, hipEvent_t *ev);
 hipError_t timed_end(nb_ctx *ctx, int cls, hipEvent_t *ev);
 int64_t bucket_log2(int64_t v);

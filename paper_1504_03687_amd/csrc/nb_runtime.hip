@@ -36,29 +36,41 @@ int hip_fail(nb_ctx *ctx, hipError_t e)
     return NB_ERR_HIP;
 }
 
-int ensure_scratch(nb_ctx *ctx, size_t bytes)
+// Grows a context-owned device buffer to at least 'bytes' (contents are not
+// kept); the scratch limit bounds each buffer.
+static int ensure_buffer(nb_ctx *ctx, void **buf, size_t *have, size_t bytes)
 {
-    if (bytes <= ctx->scratch_bytes) return NB_OK;
+    if (bytes <= *have) return NB_OK;
     if (ctx->scratch_limit && bytes > ctx->scratch_limit) return NB_ERR_OOM;
-    if (ctx->scratch) {
+    if (*buf) {
         // the old buffer may still be in use by queued work on the stream
         hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e);
-        (void)hipFree(ctx->scratch);
-        ctx->scratch = nullptr;
-        ctx->scratch_bytes = 0;
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *have = 0;
     }
     size_t want = std::max(bytes, (size_t)1 << 20);
     want = (want + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
     if (ctx->scratch_limit && want > ctx->scratch_limit) want = bytes;
-    hipError_t e = hipMalloc(&ctx->scratch, want);
+    hipError_t e = hipMalloc(buf, want);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        ctx->scratch = nullptr;
+        *buf = nullptr;
         return NB_ERR_OOM;
     }
-    ctx->scratch_bytes = want;
+    *have = want;
     return NB_OK;
+}
+
+int ensure_scratch(nb_ctx *ctx, size_t bytes)
+{
+    return ensure_buffer(ctx, &ctx->scratch, &ctx->scratch_bytes, bytes);
+}
+
+int ensure_aux(nb_ctx *ctx, size_t bytes)
+{
+    return ensure_buffer(ctx, &ctx->aux, &ctx->aux_bytes, bytes);
 }
 
 hipError_t timed_begin(nb_ctx *ctx, int cls, hipEvent_t *ev)
@@ -216,6 +228,7 @@ int nb_ctx_destroy(nb_ctx *ctx)
         (void)hipStreamSynchronize(ctx->stream);
         nbrt::batched_release(ctx);
         if (ctx->scratch) (void)hipFree(ctx->scratch);
+        if (ctx->aux) (void)hipFree(ctx->aux);
         for (auto &p : ctx->pending) {
             (void)hipEventDestroy(p.start);
             (void)hipEventDestroy(p.stop);

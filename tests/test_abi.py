@@ -176,3 +176,26 @@ def test_sched_next_matches_oracle_selection():
             lev[i] = int(rng.integers(lo, min(k_max, int(lev[i]) + 2) + 1))
         t[act] = t_new
         t_now = t_new
+
+
+def test_argument_validation_radius_control(host_ctx):
+    L = nb.lib()
+    p = _fake
+    E, U = -1, -4
+
+    def upd(ctx=host_ctx, n_i=10, cnt=p(1), rs2=p(2), nnb=64, lo=0.5, hi=2.0, out=p(3)):
+        return L.nb_radius_update(ctx, n_i, cnt, rs2, nnb, lo, hi, out)
+
+    assert upd(ctx=None) == E and upd(n_i=-1) == E and upd(nnb=0) == E
+    assert upd(lo=0.0) == E and upd(lo=-1.0) == E and upd(hi=0.25) == E
+    assert upd(hi=float("inf")) == E and upd(hi=float("nan")) == E
+    assert upd(cnt=None) == E and upd(rs2=None) == E and upd(out=None) == E
+    assert upd() == U and upd(n_i=0, cnt=None, rs2=None, out=None) == U
+
+    def fit(ctx=host_ctx, n=100, n_i=10, rs2=p(5), cap=8, prec=0, nnb=64, rounds=4, lst=p(9)):
+        return L.nb_regular_force_fit(ctx, n, p(1), p(2), p(3), n_i, p(4), rs2, cap, prec, nnb,
+                                      rounds, p(6), p(7), p(8), lst, p(10), None, None)
+
+    assert fit(ctx=None) == E and fit(cap=0) == E and fit(nnb=0) == E and fit(rounds=-1) == E
+    assert fit(lst=None) == E and fit(rs2=None) == E and fit(n=0) == E and fit(prec=3) == E
+    assert fit() == U
