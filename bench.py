@@ -125,6 +125,56 @@ def sched_leg(nb, W, s, ctx, dev, reps=20):
                   "mean_update_us": round(cyc_us / max(blocks, 1), 2)}}
 
 
+def radius_leg(nb, W, s, ctx, dev, x, v, a, jk, m, precs, L=10, cap=48, nnbopt=40):
+    """Neighbour-radius control on one step level's block of the same cluster:
+    the next-step radius update of the full block, and the regular force with
+    overflowed rows shrunk and recomputed, against the plain regular force of
+    the same block and cap."""
+    import torch
+    n = s["n"]
+    tl, t0l, bl = W.config3_level(s, L)
+    xp, vp, _ = nb.predict(x, v, a, jk, dev(t0l), tl, ctx=ctx)
+    bd = dev(bl)
+    rs2_0 = dev(s["rs2"][bl])
+    out = {"workload": f"N={n}, level {L} block ({bl.size} rows), nb_cap {cap}, "
+                       f"NNBOPT {nnbopt}, radii from the 64th neighbour"}
+    for prec in precs:
+        plain = nb.regular_force(xp, vp, m, bd, rs2_0, cap, prec, ctx=ctx)
+        over = int((plain[2] > cap).sum().item())
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        nb.regular_force(xp, vp, m, bd, rs2_0, cap, prec, ctx=ctx)
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - c1) * 1e3
+        rs2 = rs2_0.clone()
+        torch.cuda.synchronize()
+        c1 = time.perf_counter()
+        res = nb.regular_force_fit(xp, vp, m, bd, rs2, cap, nnbopt, 8, prec, ctx=ctx)
+        torch.cuda.synchronize()
+        t_fit = (time.perf_counter() - c1) * 1e3
+        out[prec] = {"plain_ms": round(t_plain, 3), "fit_ms": round(t_fit, 3),
+                     "rounds": res[5], "rows_overflowing_before": over,
+                     "overflow_after": int(res[4].item())}
+        log(f"radius fit {prec}: plain {t_plain:.2f} ms, fit {t_fit:.2f} ms, "
+            f"{over} rows overflowed, {res[5]} rounds")
+    # next-step radius update of the full 2^20 block (HBM-bound, 20 B per row)
+    full = dev(s["rs2"])
+    cnt = torch.full((n,), 70, dtype=torch.int32, device="cuda")
+    nb.radius_update(cnt, full, 64, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.reset_timing()
+    ctx.enable_timing(True)
+    for _ in range(20):
+        nb.radius_update(cnt, full, 64, ctx=ctx)
+    ums, ul = ctx.kernel_time(nb.CLASS_RADIUS)
+    ctx.enable_timing(False)
+    us = ums * 1e3 / max(ul, 1)
+    out["update_full_block_us"] = round(us, 2)
+    out["update_GB_per_s"] = round(20.0 * n / us * 1e-3, 1)
+    log(f"radius update, {n} rows: {us:.1f} us ({20.0 * n / us * 1e-3:.0f} GB/s)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +376,7 @@ def main():
 
     if not args.no_levels:
         extras["sched"] = sched_leg(nb, W, s, ctx, dev)
+        extras["radius"] = radius_leg(nb, W, s, ctx, dev, x, v, a, jk, m, precs)
 
     # CPU oracle on a bounded sample of the same full block
     cpu = None
