@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--cpu-rows", type=int, default=4096,
+    ap.add_argument("--cpu-rows", type=int, default=12288,
                     help="rows of the full block timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-levels", action="store_true")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
