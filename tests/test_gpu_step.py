@@ -125,3 +125,81 @@ def test_shared_step_integration_matches_oracle(ctx):
     dv = np.abs(host(gv) - ov).max()
     say(f"  after 8 steps: max |dx| {dx:.2e}  max |dv| {dv:.2e}")
     assert dx <= 1e-12 and dv <= 1e-11
+
+
+def test_hierarchical_block_steps_match_oracle(ctx):
+    """Individual block steps driven entirely by the library: the sorting list
+    picks each block (its prefix is the i_block), all bodies are predicted to
+    the block time from their own t0, the block gets regular + irregular force
+    and the Hermite corrector, its radii move toward NNBOPT and its bodies take
+    new step levels (seeded, shared with the oracle loop), and the list is
+    updated.  The same loop on the oracle must agree on every block's time and
+    members, on every list and radius bit for bit, and on the trajectories."""
+    import oracle.radius as R
+    import oracle.sched as S
+    say("hierarchical block steps")
+    n, cap, nnbopt, k_max = 1024, 128, 24, 12
+    s = W.small_state(97, n, k_nn=24)
+    rng = np.random.default_rng(98)
+    lev = W.sample_levels(rng, n, 4, 10, k_peak=6)
+    m = s["m"]
+    # shared initial state: full force at t = 0 from the oracle
+    allb = np.arange(n, dtype=np.int32)
+    a0, j0, *_ = oracle.regular(s["x"], s["v"], m, allb, np.zeros(n), 1)
+    ox, ov, oa, oj = s["x"].copy(), s["v"].copy(), a0.copy(), j0.copy()
+    ot, ors2, olev = np.zeros(n), s["rs2"].copy(), lev.copy()
+    gx, gv, ga, gj = dev(s["x"]), dev(s["v"]), dev(a0), dev(j0)
+    gt, grs2, glev, gm = dev(np.zeros(n)), dev(s["rs2"]), dev(lev), dev(m)
+    order, le = nb.sched_build(glev, k_max, ctx=ctx)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    T = 0.0
+    for step in range(200):
+        # oracle
+        T_new, act = S.next_block(ot, np.ldexp(1.0, -olev.astype(np.int64)))
+        xp, vp = oracle.predict(T_new, ox, ov, oa, oj, ot)
+        ra, rj, rc, rl, ovf, _ = oracle.regular(xp, vp, m, act, ors2[act], cap)
+        ia, ij = oracle.irregular(xp, vp, m, act, cap, rc, rl)
+        h = np.ldexp(1.0, -olev[act].astype(np.int64))
+        x1, v1, _, _ = oracle.hermite_correct(h, ox[:, act], ov[:, act], oa[:, act], oj[:, act],
+                                              ra + ia, rj + ij)
+        ox[:, act], ov[:, act], oa[:, act], oj[:, act] = x1, v1, ra + ia, rj + ij
+        ot[act] = T_new
+        ors2[act] = R.radius_update(ors2[act], rc, nnbopt, 0.5, 2.0)
+        L = S.due_level(T_new, k_max)
+        new = W.next_levels(rng, olev[act], L, 10)
+        olev[act] = new
+        # library
+        t_new, gL, n_a = nb.sched_next(T, k_max, host(le))
+        assert t_new == T_new and gL == L and n_a == act.size, step
+        blk = order[:n_a].clone()
+        bl = blk.long()
+        assert np.array_equal(np.sort(host(blk)), act), step
+        gxp, gvp, _ = nb.predict(gx, gv, ga, gj, gt, T_new, ctx=ctx)
+        brs2 = grs2[bl].contiguous()
+        r = nb.regular_force(gxp, gvp, gm, blk, brs2, cap, "fp64", status=st, ctx=ctx)
+        i2 = nb.irregular_force(gxp, gvp, gm, blk, cap, r[2], r[3], status=st, ctx=ctx)
+        a1, j1 = r[0] + i2[0], r[1] + i2[1]
+        hb = 1.0 / (2 ** glev[bl].long()).double()          # step 2^-level, exact
+        gx1, gv1, _, _ = nb.hermite_correct(hb, gx[:, bl].contiguous(), gv[:, bl].contiguous(),
+                                            ga[:, bl].contiguous(), gj[:, bl].contiguous(), a1, j1,
+                                            ctx=ctx)
+        gx[:, bl], gv[:, bl], ga[:, bl], gj[:, bl] = gx1, gv1, a1, j1
+        gt[bl] = T_new
+        grs2[bl] = nb.radius_update(r[2], brs2, nnbopt, 0.5, 2.0, ctx=ctx)
+        # same new levels, in list order
+        pos = np.searchsorted(act, host(blk))
+        glev[bl] = torch.from_numpy(new[pos]).cuda()
+        nb.sched_update(order, le, n_a, L, glev, k_max, status=st, ctx=ctx)
+        # lists and radii agree bit for bit with the oracle's (rows in list order)
+        cnt_g = host(r[2])
+        assert np.array_equal(cnt_g, rc[pos]), step
+        assert np.array_equal(host(grs2), ors2), step
+        T = T_new
+    torch.cuda.synchronize()
+    # a few dense-core rows may exceed nb_cap (both loops truncate alike)
+    assert int(st.item()) & ~nb.STATUS_OVERFLOW == 0
+    dx = np.abs(host(gx) - ox).max()
+    dv = np.abs(host(gv) - ov).max()
+    say(f"  T = {T}, max |dx| {dx:.2e}, max |dv| {dv:.2e}")
+    assert dx <= 1e-11 and dv <= 1e-10
+    assert np.array_equal(host(gt), ot)
