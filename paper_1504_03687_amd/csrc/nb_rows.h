@@ -433,6 +433,9 @@ __device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_
     for (int k = 0; k < 6; ++k) out[k] = block_sum(v[k], lds);
 }
 
+constexpr int kMergeBatch = 8;    // strides of split partials loaded per batch
+constexpr int kCountBatch = 16;   // segment counts loaded per batch
+
 // Merge of one row by a whole work-group, for plans with many splits: the
 // sums stride the splits over the lanes (fixed order); for the lists lane t
 // owns the contiguous splits [t*K, (t+1)*K) and a work-group prefix scan of
@@ -449,17 +452,45 @@ __device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, cons
     const int32_t s0 = tid * K;
     const int32_t s1 = s0 + K < S ? s0 + K : S;
 
-    // sums: lanes stride the splits (coalesced loads), fixed order
+    // sums: lanes stride the splits (coalesced loads), fixed order; the loads
+    // of kMergeBatch strides are issued before any is added, so a lane waits
+    // on one memory latency per batch, not per split
     double v[kSlotComp] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int32_t s = tid; s < S; s += kBlock) {
-        const int64_t slot = g.slot0 + (int64_t)s * g.slot_step;
+    for (int32_t sb = tid; sb < S; sb += kBlock * kMergeBatch) {
+        double t[kMergeBatch][kSlotComp];
 #pragma unroll
-        for (int k = 0; k < kSlotComp; ++k) v[k] += a.part[(int64_t)k * T + slot];
+        for (int u = 0; u < kMergeBatch; ++u) {
+            const int32_t s = sb + u * kBlock;
+            const int64_t slot = g.slot0 + (int64_t)(s < S ? s : 0) * g.slot_step;
+#pragma unroll
+            for (int k = 0; k < kSlotComp; ++k) t[u][k] = a.part[(int64_t)k * T + slot];
+        }
+#pragma unroll
+        for (int u = 0; u < kMergeBatch; ++u)
+            if (sb + u * kBlock < S) {
+#pragma unroll
+                for (int k = 0; k < kSlotComp; ++k) v[k] += t[u][k];
+            }
     }
     // counts: lane t owns the contiguous splits [s0, s1) so that its segments
-    // are consecutive in the row's list
+    // are consecutive in the row's list; nz marks its non-empty segments
+    // (first 64), so the copy below visits only those
     int64_t mine = 0;
-    for (int32_t s = s0; s < s1; ++s) mine += a.seg_cnt[g.slot0 + (int64_t)s * g.slot_step];
+    uint64_t nz = 0;
+    for (int32_t sb = s0; sb < s1; sb += kCountBatch) {
+        int32_t c[kCountBatch];
+#pragma unroll
+        for (int u = 0; u < kCountBatch; ++u) {
+            const int32_t s = sb + u < s1 ? sb + u : s0;
+            c[u] = a.seg_cnt[g.slot0 + (int64_t)s * g.slot_step];
+        }
+#pragma unroll
+        for (int u = 0; u < kCountBatch; ++u)
+            if (sb + u < s1) {
+                mine += c[u];
+                if (c[u] > 0 && sb + u - s0 < 64) nz |= 1ull << (sb + u - s0);
+            }
+    }
 #pragma unroll
     for (int k = 0; k < kSlotComp; ++k) v[k] = block_sum(v[k], lds);
 
@@ -480,7 +511,17 @@ __device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, cons
     if (!bad) {
         const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
         const float rs2f = (float)a.rs2[b];
-        for (int32_t s = s0; s < s1 && start < a.cap; ++s) {
+        // with at most 64 splits per lane only the marked segments are read
+        uint64_t todo = nz;
+        int32_t s = s0 - 1;
+        while (start < a.cap) {
+            if (K <= 64) {
+                if (!todo) break;
+                s = s0 + __builtin_ctzll(todo);
+                todo &= todo - 1;
+            } else if (++s >= s1) {
+                break;
+            }
             const int64_t slot = g.slot0 + (int64_t)s * g.slot_step;
             const int32_t c = a.seg_cnt[slot];
             if (c <= 0) continue;

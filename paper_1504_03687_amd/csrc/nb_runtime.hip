@@ -119,11 +119,13 @@ Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed)
     if (it != ctx->tuned.end()) return it->second;
     Plan p{};
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
-    if (n_i < 128) {
+    if (n_i < 256) {
+        // small blocks stream the j-set: ~2 waves per SIMD in total; more
+        // splits only add merge work (measured at N = 2^20, n_i = 1 .. 255)
         p.mapping = 2;
         p.rows_per_lane = n_i >= 4 ? 4 : (n_i >= 2 ? 2 : 1);
         const int64_t groups = (n_i + p.rows_per_lane - 1) / p.rows_per_lane;
-        const int64_t target = (int64_t)cus * 16;   // ~4 waves per SIMD
+        const int64_t target = (int64_t)cus * 8;
         int64_t s = (target + groups - 1) / groups;
         const int64_t max_s = std::max<int64_t>(1, n / (4 * nb::kWave));
         p.splits = (int)std::max<int64_t>(1, std::min(s, max_s));

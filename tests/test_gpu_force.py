@@ -241,3 +241,56 @@ def test_config3_million_body(ctx, level):
         say(f"  {prec} plan {ctx.last_plan()}  err acc {ea:.2e} jerk {ej:.2e}")
         del res
         torch.cuda.empty_cache()
+
+
+def _uniform_cube(seed, n):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.0, 1.0, (3, n))
+    v = rng.standard_normal((3, n)) * 0.3
+    m = rng.uniform(0.5, 1.5, n) / n
+    return x, v, m
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_many_splits_workgroup_merge(ctx, prec):
+    """Plans with >= 256 j-splits merge each row with a whole work-group:
+    sums over the splits in fixed order, segments placed by a prefix scan,
+    overflowed segments (> 96 neighbours in one split) rebuilt in order."""
+    say(f"work-group merge {prec}")
+    n = 40000
+    x, v, m = _uniform_cube(901, n)
+    centre = int(np.argmin((x ** 2).sum(axis=0)))
+    ib = np.array([centre, 17, 39999, 12345, 12345, 20000, 777], np.int32)
+    # row 0 (the body nearest the centre) holds > 90% of the bodies: more than
+    # 96 in every 128-body split
+    rs2 = np.array([1.5 ** 2, 0.05 ** 2, 0.6 ** 2, 0.01 ** 2, 0.01 ** 2, 0.0, 0.45 ** 2])
+    try:
+        for plan in ((2, 1, 400), (2, 4, 320), (2, 2, 625)):   # 313, 313, 625 splits
+            ctx.set_plan(*plan)
+            for cap in (5000, 64):
+                res = nb.regular_force(dev(x), dev(v), dev(m), dev(ib), dev(rs2), cap, prec,
+                                       ctx=ctx)
+                compare_force(res, x, v, m, ib, rs2, cap, TOL[prec])
+            assert "splits=" in ctx.last_plan()
+            assert int(ctx.last_plan().split("splits=")[1].split()[0]) >= 256
+        assert host(res[2])[0] > 0.9 * n
+    finally:
+        ctx.set_plan(0, 0, 0)
+
+
+def test_more_than_64_splits_per_merge_lane(ctx):
+    """Over 16384 splits (N > 2^20 bodies in 64-body splits) each merge lane
+    owns more than 64 segments and walks them all."""
+    say("merge with > 64 splits per lane")
+    n = (1 << 21) + 4097
+    x, v, m = _uniform_cube(902, n)
+    ib = np.array([5, n - 1, 1 << 20, 31337], np.int32)
+    rs2 = np.full(ib.size, 0.03 ** 2)
+    try:
+        ctx.set_plan(2, 1, 40000)
+        res = nb.regular_force(dev(x), dev(v), dev(m), dev(ib), dev(rs2), 256, "fp64", ctx=ctx)
+        assert int(ctx.last_plan().split("splits=")[1].split()[0]) > 64 * 256
+        compare_force(res, x, v, m, ib, rs2, 256, TOL_FP64)
+        assert host(res[2]).min() > 10
+    finally:
+        ctx.set_plan(0, 0, 0)
