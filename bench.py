@@ -44,11 +44,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("nb_internal.h", "nb_pair.h", "nb_rows.h", "nb_force.hip")
+# the kernels and the plan rules that shape their launches
+KERNEL_SOURCES = ("nb_internal.h", "nb_pair.h", "nb_rows.h", "nb_force.hip", "nb_runtime.hip")
 
 
 def kernel_src_hash() -> str:
-    """SHA-1 over the sources of the regular-force kernels."""
+    """SHA-1 over the sources of the regular-force kernels and their plans."""
     import hashlib
     h = hashlib.sha1()
     for name in KERNEL_SOURCES:
