@@ -13,6 +13,7 @@
 // (counter reset, overflow reset, persistent kernel, merge) is captured once
 // per shape into a HIP graph and replayed.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -154,6 +155,14 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     const int32_t C = (int32_t)c->j_off.size() - 1;
     std::vector<nb::BCluster> cl((size_t)C);
     int64_t slots = 0;
+    // automatic splits: items of at most ~1/(64 per CU) of the total pair
+    // work, so the queue's tail is short (as for single blocks), with
+    // splits of at least 8 tiles
+    double total_work = 0.0;
+    for (int32_t k = 0; k < C; ++k)
+        total_work += (double)(c->i_off[k + 1] - c->i_off[k]) * (double)(c->j_off[k + 1] - c->j_off[k]);
+    const double item_work =
+        std::max(1.0, total_work / ((ctx->cu_count > 0 ? ctx->cu_count : 256) * 64.0));
     for (int32_t k = 0; k < C; ++k) {
         const int64_t nc = c->j_off[k + 1] - c->j_off[k];
         const int64_t rc = c->i_off[k + 1] - c->i_off[k];
@@ -163,7 +172,9 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
         } else if (c->forced_splits > 0) {
             S = std::min<int64_t>(c->forced_splits, (nc + nb::kTile - 1) / nb::kTile);
         } else {
-            S = (nc + 65535) / 65536;   // bounds the largest item's work
+            const double rows = (double)std::min<int64_t>(rc, (int64_t)c->rows_per_lane * nb::kBlock);
+            S = (int64_t)std::ceil(rows * (double)nc / item_work);
+            S = std::max<int64_t>(1, std::min<int64_t>(S, nc / (8 * nb::kTile)));
         }
         const int64_t tiles = std::max<int64_t>(1, (nc + nb::kTile - 1) / nb::kTile);
         const int64_t per = (tiles + S - 1) / S;

@@ -109,16 +109,17 @@ def test_batched_graph_replay_sees_new_data(ctx):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batched_equals_single_launches(ctx, prec):
+@pytest.mark.parametrize("splits", [1, 3])
+def test_batched_equals_single_launches(ctx, prec, splits):
     """Each cluster of the batch gives bit-identical rows to a single-block
     launch of the same plan on that cluster alone."""
-    say(f"batched vs single {prec}")
+    say(f"batched vs single {prec} splits={splits}")
     E = _ensemble(seed=11)
-    out = [host(t) for t in nb.regular_force_batched(
-        E["j_off"], E["i_off"], dev(E["x"]), dev(E["v"]), dev(E["m"]), dev(E["ib"]),
-        dev(E["rs2"]), 32, prec, ctx=ctx)]
-    ctx.set_plan(1, 1, 1)
+    ctx.set_plan(1, 1, splits)
     try:
+        out = [host(t) for t in nb.regular_force_batched(
+            E["j_off"], E["i_off"], dev(E["x"]), dev(E["v"]), dev(E["m"]), dev(E["ib"]),
+            dev(E["rs2"]), 32, prec, ctx=ctx)]
         for c in range(len(E["j_off"]) - 1):
             j0, j1 = E["j_off"][c], E["j_off"][c + 1]
             r0, r1 = E["i_off"][c], E["i_off"][c + 1]
