@@ -446,14 +446,16 @@ int nb_regular_force_adjoint(nb_ctx *ctx, int64_t n, const double *xp, const dou
     if (n_i > 0 && (!i_block || !rs2 || !w_a || !w_j)) return NB_ERR_INVALID_ARG;
     if (!ctx->usable) return NB_ERR_UNSUPPORTED;
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
-    const int64_t target = (int64_t)cus * 8;
+    // as for the forward pass: many short work-groups (~64 per CU in total),
+    // with at least 2048 bodies (row pass) or 512 rows (body pass) per split
+    const int64_t target = (int64_t)cus * 64;
     const int64_t row_wgs = std::max<int64_t>(1, (n_i + nb::kBlock - 1) / nb::kBlock);
     const int64_t body_wgs = (n + nb::kBlock - 1) / nb::kBlock;
     int row_splits = (int)std::max<int64_t>(
-        1, std::min<int64_t>((target + row_wgs - 1) / row_wgs, std::max<int64_t>(1, n / 1024)));
+        1, std::min<int64_t>((target + row_wgs - 1) / row_wgs, std::max<int64_t>(1, n / 2048)));
     int body_splits = (int)std::max<int64_t>(
         1, std::min<int64_t>((target + body_wgs - 1) / body_wgs,
-                             std::max<int64_t>(1, (n_i + 127) / 128)));
+                             std::max<int64_t>(1, (n_i + 511) / 512)));
     int rc = ensure_scratch(ctx, nb::adjoint_scratch_bytes(n, n_i, row_splits, body_splits));
     if (rc != NB_OK) return rc;
     nb::AdjointArgs aa{};
