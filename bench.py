@@ -45,7 +45,7 @@ def log(*a):
 
 
 # the kernels and the plan rules that shape their launches
-KERNEL_SOURCES = ("nb_internal.h", "nb_pair.h", "nb_rows.h", "nb_force.hip", "nb_runtime.hip")
+KERNEL_SOURCES = ("nb_internal.h", "nb_pair.h", "nb_rows.h", "nb_force.hip", "nb_plan.hip")
 
 
 def kernel_src_hash() -> str:
