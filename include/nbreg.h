@@ -257,8 +257,10 @@ int nb_radius_update(nb_ctx *ctx, int32_t n_i, const int32_t *nb_count, const do
  * target = min(nnbopt, nb_cap), and those rows alone are recomputed with the
  * new radii (their acc, jerk, count and list replace the old ones).  rs2 is
  * IN/OUT: the caller's array holds the final radii.  Rounds stop when no row
- * overflows; *overflow reports the final state.  Each round synchronises the
- * stream twice (to read the overflow word and the number of rows).
+ * overflows; *overflow reports the final state (status, which is only ever
+ * OR-ed, keeps NB_STATUS_OVERFLOW from a round even when a later round
+ * resolved it).  Each round synchronises the stream twice (to read the
+ * overflow word and the number of rows).
  * rounds_host (optional, host) receives the number of rounds made.  Rows are
  * recomputed in ascending row order, so results are deterministic and a row's
  * result equals a plain nb_regular_force call with its final radius.
