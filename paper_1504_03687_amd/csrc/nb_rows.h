@@ -83,49 +83,85 @@ __device__ __forceinline__ void row_init(Row<MIXED> &R, const ForceArgs &a, int6
     }
 }
 
-// One (row, body) pair in the row-per-lane mapping: lane-private append.
+// Row-per-lane mapping: each lane appends to its own row's list (in j order).
+// Rare branch of a mixed pair (neighbour, self or near pair): appends a
+// neighbour, or adds a near pair's term in FP64.
 template <bool MIXED>
-__device__ __forceinline__ void pair_rows(Row<MIXED> &R, const JBody &J, int32_t jidx)
+__device__ __forceinline__ void rare_mixed(Row<MIXED> &R, const JBody &J, int32_t jidx, float r2f,
+                                           double dx, double dy, double dz)
 {
-    const double dx = J.x - R.x, dy = J.y - R.y, dz = J.z - R.z;
+    double ex = dx, ey = dy, ez = dz;
+    int32_t jj = jidx;
+    opaque(ex, ey, ez);
+    opaque(jj);
+    const bool self = jj == R.i;
+    const bool nbr = (r2f < R.rs2f) && !self;
+    if (nbr) {
+        if (R.cnt < R.lcap) R.lst[R.cnt] = jidx;
+        ++R.cnt;
+    } else if (!self) {
+        add_term_f64(R.S.ax, R.S.ay, R.S.az, R.S.jx, R.S.jy, R.S.jz, ex, ey, ez,
+                     J.vx - R.vx, J.vy - R.vy, J.vz - R.vz, J.m);
+    }
+}
+
+// Exact canonical test of an FP64 candidate pair; appends a neighbour.
+// Returns true if the pair is excluded (neighbour or self).
+template <bool MIXED>
+__device__ __forceinline__ bool rare_f64(Row<MIXED> &R, int32_t jidx, double dx, double dy,
+                                         double dz)
+{
+    double ex = dx, ey = dy, ez = dz;
+    int32_t jj = jidx;
+    opaque(ex, ey, ez);
+    opaque(jj);
+    const bool self = jj == R.i;
+    const bool nbr = (canon_r2f(ex, ey, ez) < R.rs2f) && !self;
+    if (nbr) {
+        if (R.cnt < R.lcap) R.lst[R.cnt] = jidx;
+        ++R.cnt;
+    }
+    return nbr || self;
+}
+
+// One row against two consecutive j, with a single branch for the rare cases
+// (one exec-mask change per two j).  Mixed: FP64 differences, canonical FP32
+// r2f (the neighbour test itself), FP32 terms; pairs with r2f below the
+// near bound (neighbours, self, near pairs) take the rare branch.  FP64: FP64
+// r2 against the candidate bound, the exact canonical test only for
+// candidates.  Every accumulator receives the terms of j and then j+1, as a
+// loop over single j would give them.
+template <bool MIXED>
+__device__ __forceinline__ void pair_rows2(Row<MIXED> &R, const JBody &J0, const JBody &J1,
+                                           int32_t jidx0)
+{
     if constexpr (MIXED) {
-        const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-        const float r2f = __builtin_fmaf(fz, fz, __builtin_fmaf(fy, fy, fx * fx));
-        bool excl = false;
-        if (r2f < R.candf) {   // neighbour, self, or near pair (FP64 term)
-            double ex = dx, ey = dy, ez = dz;
-            int32_t jj = jidx;
-            opaque(ex, ey, ez);
-            opaque(jj);
-            const bool self = jj == R.i;
-            const bool nbr = (r2f < R.rs2f) && !self;
-            if (nbr) {
-                if (R.cnt < R.lcap) R.lst[R.cnt] = jidx;
-                ++R.cnt;
-            } else if (!self) {
-                add_term_f64(R.S.ax, R.S.ay, R.S.az, R.S.jx, R.S.jy, R.S.jz, ex, ey, ez,
-                             J.vx - R.vx, J.vy - R.vy, J.vz - R.vz, J.m);
-            }
-            excl = true;
+        const double dx0 = J0.x - R.x, dy0 = J0.y - R.y, dz0 = J0.z - R.z;
+        const double dx1 = J1.x - R.x, dy1 = J1.y - R.y, dz1 = J1.z - R.z;
+        const float fx0 = (float)dx0, fy0 = (float)dy0, fz0 = (float)dz0;
+        const float fx1 = (float)dx1, fy1 = (float)dy1, fz1 = (float)dz1;
+        const float r0 = __builtin_fmaf(fz0, fz0, __builtin_fmaf(fy0, fy0, fx0 * fx0));
+        const float r1 = __builtin_fmaf(fz1, fz1, __builtin_fmaf(fy1, fy1, fx1 * fx1));
+        const bool c0 = r0 < R.candf, c1 = r1 < R.candf;
+        if (c0 || c1) {
+            if (c0) rare_mixed<MIXED>(R, J0, jidx0, r0, dx0, dy0, dz0);
+            if (c1) rare_mixed<MIXED>(R, J1, jidx0 + 1, r1, dx1, dy1, dz1);
         }
-        accum_mixed(R.S, fx, fy, fz, r2f, J.vx - R.vx, J.vy - R.vy, J.vz - R.vz, J.m32, excl);
+        accum_mixed(R.S, fx0, fy0, fz0, r0, J0.vx - R.vx, J0.vy - R.vy, J0.vz - R.vz, J0.m32, c0);
+        accum_mixed(R.S, fx1, fy1, fz1, r1, J1.vx - R.vx, J1.vy - R.vy, J1.vz - R.vz, J1.m32, c1);
     } else {
-        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        bool excl = false;
-        if (r2 < R.hi) {
-            double ex = dx, ey = dy, ez = dz;
-            int32_t jj = jidx;
-            opaque(ex, ey, ez);
-            opaque(jj);
-            const bool self = jj == R.i;
-            const bool nbr = (canon_r2f(ex, ey, ez) < R.rs2f) && !self;
-            if (nbr) {
-                if (R.cnt < R.lcap) R.lst[R.cnt] = jidx;
-                ++R.cnt;
-            }
-            excl = nbr || self;
+        const double dx0 = J0.x - R.x, dy0 = J0.y - R.y, dz0 = J0.z - R.z;
+        const double dx1 = J1.x - R.x, dy1 = J1.y - R.y, dz1 = J1.z - R.z;
+        const double r0 = __builtin_fma(dz0, dz0, __builtin_fma(dy0, dy0, dx0 * dx0));
+        const double r1 = __builtin_fma(dz1, dz1, __builtin_fma(dy1, dy1, dx1 * dx1));
+        const bool c0 = r0 < R.hi, c1 = r1 < R.hi;
+        bool e0 = false, e1 = false;
+        if (c0 || c1) {
+            if (c0) e0 = rare_f64<MIXED>(R, jidx0, dx0, dy0, dz0);
+            if (c1) e1 = rare_f64<MIXED>(R, jidx0 + 1, dx1, dy1, dz1);
         }
-        accum_f64(R.S, dx, dy, dz, r2, J.vx - R.vx, J.vy - R.vy, J.vz - R.vz, J.m, excl);
+        accum_f64(R.S, dx0, dy0, dz0, r0, J0.vx - R.vx, J0.vy - R.vy, J0.vz - R.vz, J0.m, e0);
+        accum_f64(R.S, dx1, dy1, dz1, r1, J1.vx - R.vx, J1.vy - R.vy, J1.vz - R.vz, J1.m, e1);
     }
 }
 
@@ -239,12 +275,11 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTil
         if (t + 1 < ntiles) load_body(nxt, a, tbase + kTile + tid, j1);
         const JBody *buf = tile[cur];
         for (int jj = 0; jj < kTile; jj += kFold) {
-#pragma unroll 2
-            for (int q = 0; q < kFold; ++q) {
-                const JBody &J = buf[jj + q];
+            for (int q = 0; q < kFold; q += 2) {
                 const int32_t jidx = (int32_t)(tbase + jj + q);
 #pragma unroll
-                for (int r = 0; r < IR; ++r) pair_rows<MIXED>(R[r], J, jidx);
+                for (int r = 0; r < IR; ++r)
+                    pair_rows2<MIXED>(R[r], buf[jj + q], buf[jj + q + 1], jidx);
             }
             if constexpr (MIXED) {
 #pragma unroll
