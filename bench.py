@@ -176,6 +176,57 @@ def radius_leg(nb, W, s, ctx, dev, x, v, a, jk, m, precs, L=10, cap=48, nnbopt=4
     return out
 
 
+def step_leg(nb, s, ctx, x, v, a, jk, m, xp, vp, ibd, out, t, t0d):
+    """The rest of the Ahmad-Cohen block step at the full 2^20 block: the
+    irregular force over the lists of the regular pass just timed (gathers),
+    the Hermite corrector (streaming) and the O(N^2) potential (FP64 ALU).
+    Each figure is the library's own HIP-event time of that kernel class."""
+    import torch
+    n = s["n"]
+    cap = s["nb_cap"]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ctx.reset_timing()
+        ctx.enable_timing(True)
+        for _ in range(reps):
+            fn()
+        ms, calls = ctx.kernel_time(nb.CLASS_STEP)
+        ctx.enable_timing(False)
+        return ms / max(calls, 1)
+
+    # the lists in `out` belong to the full block at time t: predict to t again
+    nb.predict(x, v, a, jk, t0d, t, out=(xp, vp), ctx=ctx)
+    res = {}
+    pairs = float(out[2].clamp(max=cap).sum().item())
+    ms = timed(lambda: nb.irregular_force(xp, vp, m, ibd, cap, out[2], out[3], ctx=ctx), 5)
+    # algorithmic bytes per neighbour pair: the neighbour's xp, vp, m (56 B) and its
+    # list entry (4 B); the rows' own state is negligible
+    res["irregular"] = {"ms": round(ms, 4), "pairs": pairs,
+                        "gpairs_per_s": round(pairs / ms * 1e-6, 2),
+                        "roofline": {"bound": "hbm", "achieved": round(60.0 * pairs / ms * 1e-6, 1),
+                                     "peak": 8000.0, "unit": "GB/s",
+                                     "frac": round(60.0 * pairs / ms * 1e-6 / 8000.0, 4)}}
+    h = torch.full((n,), 2.0 ** -10, dtype=torch.float64, device="cuda")
+    ms = timed(lambda: nb.hermite_correct(h, x, v, a, jk, out[0], out[1], ctx=ctx), 10)
+    # 1 + 6 x 3 doubles read, 4 x 3 written per entry
+    res["corrector"] = {"ms": round(ms, 4), "entries": n,
+                        "roofline": {"bound": "hbm", "achieved": round(248.0 * n / ms * 1e-6, 1),
+                                     "peak": 8000.0, "unit": "GB/s",
+                                     "frac": round(248.0 * n / ms * 1e-6 / 8000.0, 4)}}
+    ms = timed(lambda: nb.potential(x, m, ctx=ctx), 1)
+    pp = float(n) * (n - 1)
+    # 11 flops per pair: 3 differences, r2 5, rsqrt 1, the m/r accumulation 2
+    res["potential"] = {"ms": round(ms, 3), "gpairs_per_s": round(pp / ms * 1e-6, 2),
+                        "roofline": {"bound": "alu", "achieved": round(11.0 * pp / ms * 1e-9, 2),
+                                     "peak": PEAK_FP64, "unit": "TFLOP/s",
+                                     "frac": round(11.0 * pp / ms * 1e-9 / PEAK_FP64, 4)}}
+    log(f"step: irregular {res['irregular']['ms']:.3f} ms ({res['irregular']['gpairs_per_s']} G pairs/s), "
+        f"corrector {res['corrector']['ms']:.3f} ms, potential {res['potential']['ms']:.1f} ms")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +237,9 @@ def main():
                     help="rows of the full block timed on the CPU oracle (0 = skip)")
     ap.add_argument("--no-levels", action="store_true")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only time the rest of the block step (irregular force, corrector, "
+                         "potential) at the full block and print its figures")
     ap.add_argument("--sched-only", action="store_true",
                     help="only time the block-step scheduler on the same cluster's levels "
                          "and print its figures (used for kernel profiles)")
@@ -238,6 +292,12 @@ def main():
            torch.empty((n_i, cap), dtype=torch.int32, device="cuda"),
            torch.empty(1, dtype=torch.int32, device="cuda"))
     ctx = nb.Context(0)
+    if args.step_only:
+        nb.predict(x, v, a, jk, t0d, t, out=(xp, vp), ctx=ctx)
+        nb.regular_force(xp, vp, m, ibd, rs2d, cap, "mixed", out=out, ctx=ctx)
+        print(json.dumps({"step": step_leg(nb, s, ctx, x, v, a, jk, m, xp, vp, ibd, out, t,
+                                           t0d)}), flush=True)
+        return
     if args.sched_only:
         print(json.dumps({"sched": sched_leg(nb, W, s, ctx, dev)}), flush=True)
         return
@@ -376,6 +436,7 @@ def main():
             del o4
 
     if not args.no_levels:
+        extras["step"] = step_leg(nb, s, ctx, x, v, a, jk, m, xp, vp, ibd, out, t, t0d)
         extras["sched"] = sched_leg(nb, W, s, ctx, dev)
         extras["radius"] = radius_leg(nb, W, s, ctx, dev, x, v, a, jk, m, precs)
 

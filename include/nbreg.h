@@ -97,8 +97,8 @@ int nb_ctx_set_scratch_limit(nb_ctx *ctx, int64_t bytes);
  * synchronises those events and returns the summed milliseconds and the
  * launch count of one kernel class since the last reset (class 0 = regular
  * force main kernel, 1 = cross-split reduce, 2 = predictor, 3 = adjoint,
- * 4 = batched, 5 = mixed-precision FP64 refinement, 6 = irregular force
- * and potential, 7 = block-step scheduler, 8 = radius control: update,
+ * 4 = batched, 5 = mixed-precision FP64 refinement, 6 = irregular force,
+ * corrector and potential, 7 = block-step scheduler, 8 = radius control: update,
  * compaction and scatter; the recomputed rows count under 0, 1, 5). */
 int nb_ctx_enable_timing(nb_ctx *ctx, int on);
 int nb_ctx_kernel_time(nb_ctx *ctx, int kernel_class, double *ms, int64_t *launches);

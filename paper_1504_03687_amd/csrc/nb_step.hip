@@ -2,7 +2,8 @@
 // 2015, section 2; Table 1 "Irr." and "Adjust"):
 //  * irregular force + jerk over each row's neighbour list (the bodies inside
 //    the neighbour radius, section 2), FP64, one wave per row with the list
-//    spread over the lanes (gathers from the SoA planes);
+//    spread over the lanes; gathers from the SoA planes, or for large blocks
+//    from a packed copy of the bodies (one cache line per neighbour);
 //  * the fourth-order Hermite corrector of the integrator (section 2), FP64,
 //    one thread per entry, with the second and third force derivatives from
 //    the cubic Hermite interpolant (used by step-size criteria);
@@ -16,8 +17,55 @@
 namespace nb {
 namespace {
 
+// Where the irregular force reads neighbour bodies from: the SoA planes
+// (seven cache lines per neighbour) or a packed copy with one 64-byte record
+// per body {x, y, z, m | vx, vy, vz, 0} (one line per neighbour).
+struct SoaBodies {
+    const double *xp, *vp, *m;
+    int64_t n;
+    __device__ __forceinline__ void load(int64_t j, double &x, double &y, double &z, double &vx,
+                                         double &vy, double &vz, double &mj) const
+    {
+        x = xp[j];
+        y = xp[n + j];
+        z = xp[2 * n + j];
+        vx = vp[j];
+        vy = vp[n + j];
+        vz = vp[2 * n + j];
+        mj = m[j];
+    }
+};
+
+struct PackedBodies {
+    const double4 *p;
+    __device__ __forceinline__ void load(int64_t j, double &x, double &y, double &z, double &vx,
+                                         double &vy, double &vz, double &mj) const
+    {
+        const double4 a = p[2 * j], b = p[2 * j + 1];
+        x = a.x;
+        y = a.y;
+        z = a.z;
+        mj = a.w;
+        vx = b.x;
+        vy = b.y;
+        vz = b.z;
+    }
+};
+
+__global__ __launch_bounds__(256) void pack_bodies_kernel(int64_t n, const double *xp,
+                                                          const double *vp, const double *m,
+                                                          double4 *out)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        out[2 * j] = make_double4(xp[j], xp[n + j], xp[2 * n + j], m[j]);
+        out[2 * j + 1] = make_double4(vp[j], vp[n + j], vp[2 * n + j], 0.0);
+    }
+}
+
+template <class Bodies>
 __global__ __launch_bounds__(kBlock) void irregular_kernel(int64_t n, const double *xp,
-                                                           const double *vp, const double *m,
+                                                           const double *vp, Bodies B,
                                                            int32_t n_i, const int32_t *i_block,
                                                            int32_t cap, const int32_t *nb_count,
                                                            const int32_t *nb_list, double *acc,
@@ -41,8 +89,10 @@ __global__ __launch_bounds__(kBlock) void irregular_kernel(int64_t n, const doub
                 bad = true;
                 continue;
             }
-            add_term_f64(ax, ay, az, jx, jy, jz, xp[j] - xi, xp[n + j] - yi, xp[2 * n + j] - zi,
-                         vp[j] - vxi, vp[n + j] - vyi, vp[2 * n + j] - vzi, m[j]);
+            double x, y, z, vx, vy, vz, mj;
+            B.load(j, x, y, z, vx, vy, vz, mj);
+            add_term_f64(ax, ay, az, jx, jy, jz, x - xi, y - yi, z - zi, vx - vxi, vy - vyi,
+                         vz - vzi, mj);
         }
     }
     ax = wave_sum(ax);
@@ -216,12 +266,29 @@ int nb_irregular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *v
     if (!ctx->usable) return NB_ERR_UNSUPPORTED;
     if (n_i == 0) return NB_OK;
     const int per = nb::kBlock / nb::kWave;
+    const dim3 grid((unsigned)((n_i + per - 1) / per));
+    // large blocks gather many neighbours per body: pack the bodies once into
+    // 64-byte records (one cache line per gather instead of seven)
+    const bool pack = (int64_t)n_i * 128 >= n;
+    if (pack) {
+        const int rc = ensure_scratch(ctx, (size_t)n * 2 * sizeof(double4));
+        if (rc != NB_OK) return rc;
+    }
     hipEvent_t ev[2];
     hipError_t e = timed_begin(ctx, NB_CLASS_STEP, ev);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(nb::irregular_kernel, dim3((unsigned)((n_i + per - 1) / per)),
-                           dim3(nb::kBlock), 0, ctx->stream, n, xp, vp, m, n_i, i_block, nb_cap,
-                           nb_count, nb_list, acc, jerk, status);
+    if (e == hipSuccess && pack) {
+        double4 *packed = (double4 *)ctx->scratch;
+        const unsigned pg = (unsigned)std::min<int64_t>(8192, (n + 255) / 256);
+        hipLaunchKernelGGL(nb::pack_bodies_kernel, dim3(pg), dim3(256), 0, ctx->stream, n, xp, vp,
+                           m, packed);
+        hipLaunchKernelGGL(nb::irregular_kernel<nb::PackedBodies>, grid, dim3(nb::kBlock), 0,
+                           ctx->stream, n, xp, vp, nb::PackedBodies{packed}, n_i, i_block,
+                           nb_cap, nb_count, nb_list, acc, jerk, status);
+        e = hipGetLastError();
+    } else if (e == hipSuccess) {
+        hipLaunchKernelGGL(nb::irregular_kernel<nb::SoaBodies>, grid, dim3(nb::kBlock), 0,
+                           ctx->stream, n, xp, vp, nb::SoaBodies{xp, vp, m, n}, n_i, i_block,
+                           nb_cap, nb_count, nb_list, acc, jerk, status);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_STEP, ev);
@@ -238,9 +305,14 @@ int nb_hermite_correct(nb_ctx *ctx, int64_t n, const double *h, const double *x0
     if (!ctx->usable) return NB_ERR_UNSUPPORTED;
     const int64_t want = (n + 255) / 256;
     const unsigned grid = (unsigned)(want < 65536 ? want : 65536);
-    hipLaunchKernelGGL(nb::corrector_kernel, dim3(grid), dim3(256), 0, ctx->stream, n, h, x0, v0,
-                       a0, j0, a1, j1, x1, v1, a2, a3);
-    hipError_t e = hipGetLastError();
+    hipEvent_t ev[2];
+    hipError_t e = timed_begin(ctx, NB_CLASS_STEP, ev);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(nb::corrector_kernel, dim3(grid), dim3(256), 0, ctx->stream, n, h, x0,
+                           v0, a0, j0, a1, j1, x1, v1, a2, a3);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_STEP, ev);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
 }
 

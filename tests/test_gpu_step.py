@@ -44,6 +44,22 @@ def test_irregular_force_and_full_force(ctx):
         assert e.max() <= 1e-11, e.max()
 
 
+def test_irregular_packed_and_plane_gathers_agree(ctx):
+    """Large blocks gather neighbours from a packed copy of the bodies, small
+    ones from the SoA planes: the same rows give bitwise-equal results."""
+    s = W.config2()
+    xp, vp, m = dev(s["x"]), dev(s["v"]), dev(s["m"])
+    blk = s["blocks"][16384]
+    cap = 128
+    reg = nb.regular_force(xp, vp, m, dev(blk), dev(s["rs2"][blk]), cap, "fp64", ctx=ctx)
+    big = nb.irregular_force(xp, vp, m, dev(blk), cap, reg[2], reg[3], ctx=ctx)   # packed
+    sub = np.array([0, 5, 777, 16383], np.int64)
+    small = nb.irregular_force(xp, vp, m, dev(blk[sub]), cap, reg[2][sub].contiguous(),
+                               reg[3][sub].contiguous(), ctx=ctx)               # planes
+    for g, q in zip(big, small):
+        assert np.array_equal(host(g)[:, sub], host(q))
+
+
 def test_irregular_bad_list_entry(ctx):
     s = W.small_state(91, 300)
     ib = np.array([3, 4], np.int32)
