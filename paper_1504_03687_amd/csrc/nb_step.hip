@@ -193,14 +193,27 @@ __global__ __launch_bounds__(kBlock) void potential_kernel(int64_t n, const doub
         const int64_t tbase = j0 + t * kTile;
         if (t + 1 < ntiles) load(tbase + kTile + tid);
         const PBody *buf = tile[cur];
+        // only a tile that overlaps this work-group's own rows can hold a
+        // lane's self pair (uniform per work-group)
+        const int64_t row0 = (int64_t)blockIdx.x * kBlock;
+        if (tbase < row0 + kBlock && row0 < tbase + kTile) {
 #pragma unroll 4
-        for (int jj = 0; jj < kTile; ++jj) {
-            const PBody &J = buf[jj];
-            const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
-            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-            double y = rsqrt_f64(r2);
-            y = (tbase + jj == i) ? 0.0 : y;
-            phi = __builtin_fma(-J.m, y, phi);
+            for (int jj = 0; jj < kTile; ++jj) {
+                const PBody &J = buf[jj];
+                const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                double y = rsqrt_f64(r2);
+                y = (tbase + jj == i) ? 0.0 : y;
+                phi = __builtin_fma(-J.m, y, phi);
+            }
+        } else {
+#pragma unroll 4
+            for (int jj = 0; jj < kTile; ++jj) {
+                const PBody &J = buf[jj];
+                const double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                phi = __builtin_fma(-J.m, rsqrt_f64(r2), phi);
+            }
         }
         if (t + 1 < ntiles) tile[cur ^ 1][tid] = nxt;
         __syncthreads();
@@ -323,8 +336,8 @@ int nb_potential(nb_ctx *ctx, int64_t n, const double *x, const double *m, doubl
     if (!ctx->usable) return NB_ERR_UNSUPPORTED;
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
     const int64_t wgs = (n + nb::kBlock - 1) / nb::kBlock;
-    int64_t splits = std::max<int64_t>(1, std::min<int64_t>((cus * 8 + wgs - 1) / wgs,
-                                                             std::max<int64_t>(1, n / 1024)));
+    int64_t splits = std::max<int64_t>(1, std::min<int64_t>((cus * 64 + wgs - 1) / wgs,
+                                                             std::max<int64_t>(1, n / 2048)));
     const int64_t tiles = (n + nb::kTile - 1) / nb::kTile;
     const int64_t split_len = (tiles + splits - 1) / splits * nb::kTile;
     splits = (n + split_len - 1) / split_len;
