@@ -367,11 +367,18 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
             const int64_t start = off + inc - c;
             const bool room = c > 0 && start < a.cap;
             const bool rebuild = room && c > kSegCap;
-            if (room && !rebuild) {
-                const int64_t take = (int64_t)c < a.cap - start ? c : a.cap - start;
-                const int32_t *src = a.seg_list + slot * kSegCap;
-                int32_t *dst = a.nb_list + b * (int64_t)a.cap + start;
-                for (int64_t q = 0; q < take; ++q) dst[q] = src[q];
+            // segments that fit: the whole wave copies each one (coalesced)
+            const int64_t take = room ? ((int64_t)c < a.cap - start ? c : a.cap - start) : 0;
+            uint64_t cp = __ballot(room && !rebuild);
+            while (cp) {
+                const int q = __builtin_ctzll(cp);
+                cp &= cp - 1;
+                const int64_t sl = __shfl(slot, q, kWave);
+                const int64_t st = __shfl(start, q, kWave);
+                const int64_t tk = __shfl(take, q, kWave);
+                const int32_t *src = a.seg_list + sl * kSegCap;
+                int32_t *dst = a.nb_list + b * (int64_t)a.cap + st;
+                for (int64_t e = lane; e < tk; e += kWave) dst[e] = src[e];
             }
             uint64_t rb = __ballot(rebuild);
             while (rb) {   // overflowed segments: the wave rescans them one by one
