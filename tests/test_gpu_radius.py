@@ -119,3 +119,29 @@ def test_fit_config2_block(ctx):
         ea, ej = _compare_fit(got, ref, cap, TOL[prec])
         say(f"  {prec}: rounds {got[5]}, rows shrunk {(ref[5] < rs2).sum()}, "
             f"err {ea:.2e} {ej:.2e}")
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_fit_bench_configuration_sampled(ctx, prec):
+    """The fit as the benchmark runs it: N = 2^20 (config 3), the level-10
+    block (51374 rows), radii from the 64th neighbour, nb_cap 48, NNBOPT 40.
+    Rows are independent in the fit, so the oracle's fit of 256 sampled rows
+    alone must give those rows' radii, counts and lists bit for bit."""
+    say(f"fit at the benchmark configuration {prec}")
+    s = W.config3()
+    t, t0, blk = W.config3_level(s, 10)
+    xp, vp, _ = nb.predict(dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(t0), t,
+                           ctx=ctx)
+    ox, ov = oracle.predict(t, s["x"], s["v"], s["a"], s["jk"], t0)
+    rs2 = s["rs2"][blk].copy()
+    g_rs2 = dev(rs2)
+    got = nb.regular_force_fit(xp, vp, dev(s["m"]), dev(blk), g_rs2, 48, 40, 8, prec, ctx=ctx)
+    assert int(host(got[4])[0]) == 0
+    rows = np.sort(np.random.default_rng(870).choice(blk.size, 256, replace=False))
+    ref = R.regular_fit(ox, ov, s["m"], blk[rows], rs2[rows], 48, 40, 8)
+    assert np.array_equal(host(g_rs2)[rows], ref[5])
+    check_lists(host(got[2])[rows], host(got[3])[rows], ref[2], ref[3], 48)
+    ea = row_rel_err(host(got[0])[:, rows], ref[0])
+    ej = row_rel_err(host(got[1])[:, rows], ref[1])
+    say(f"  rounds {got[5]}, sampled err acc {ea.max():.2e} jerk {ej.max():.2e}")
+    assert ea.max() <= TOL[prec] and ej.max() <= TOL[prec]

@@ -173,3 +173,22 @@ def test_prefix_is_the_force_block(ctx):
     res = nb.regular_force(xp, vp, m, blk, rs2, 64, "fp64", ctx=ctx)
     compare_force(res, s["x"], s["v"], s["m"], host(blk), host(rs2), 64, TOL_FP64)
     assert np.array_equal(np.sort(host(blk)), np.nonzero(lev >= L)[0])
+
+
+def test_bench_configuration_levels(ctx):
+    """The scheduler as the benchmark runs it: config 3's own step levels
+    (2^20 bodies, levels 3..20, k_max 20): the build is the oracle's list bit
+    for bit, and each level's update keeps every level block's members."""
+    s = W.config3()
+    lev = s["levels"].astype(np.int32)
+    k_max = 20
+    g_lev = dev(lev)
+    order, le = nb.sched_build(g_lev, k_max, ctx=ctx)
+    o_order, o_le = S.sort_list(lev, k_max)
+    assert np.array_equal(host(order), o_order) and np.array_equal(host(le), o_le)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for L in (20, 14, 5, 3):
+        nb.sched_update(order, le, int(o_le[L]), L, g_lev, k_max, status=st, ctx=ctx)
+        _segments_match(host(order), host(le), lev, k_max)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
