@@ -14,6 +14,7 @@ Parity status per function (what pins it; see tests/test_oracle_pins.py):
                       derivative of the force (pinned)
   irregular        -- regular + irregular = full force at rs2 = 0 (pinned)
   potential        -- two-body closed form, Plummer energy -1/2 (pinned)
+  potential_rows   -- two-body and three-body closed forms (pinned)
   adjoint          -- central differences of local losses (pinned)
   local_loss       -- linear in m; equals the sum of pair losses (pinned)
   hermite_correct  -- exact for cubic force histories, two-body orbit
@@ -68,6 +69,8 @@ def lib():
         L.or_irregular.restype = None
         L.or_potential.argtypes = [i64, _D, _D, _D]
         L.or_potential.restype = dbl
+        L.or_potential_rows.argtypes = [i64, _D, _D, i64, _I, _D]
+        L.or_potential_rows.restype = None
         L.or_adjoint.argtypes = [i64, _D, _D, _D, _D, i32, _I, _D, _D, _D, _D, _D, _D]
         L.or_adjoint.restype = None
         L.or_local_loss.argtypes = [i64, _D, _D, _D, _D, i32, _I, _D, _D, _D, i64]
@@ -132,6 +135,14 @@ def potential(x, m):
     phi = np.empty(m.size)
     U = lib().or_potential(m.size, x, m, phi)
     return U, phi
+
+
+def potential_rows(x, m, rows):
+    """phi at the given bodies only (same sum as ``potential``)."""
+    x, m, rows = _f64(x), _f64(m), _i32(rows)
+    phi = np.empty(rows.size)
+    lib().or_potential_rows(m.size, x, m, rows.size, rows, phi)
+    return phi
 
 
 def adjoint(xp, vp, m, i_block, rs2, w_a, w_j, xm=None):

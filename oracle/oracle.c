@@ -225,6 +225,25 @@ double or_potential(int64_t n, const double *x, const double *m, double *phi)
     return cs_get(&u);
 }
 
+/* Potential at selected bodies only: phi_r = -sum_{j != rows[r]} m_j / |x_j -
+ * x_i|, i = rows[r], the same sum as or_potential for one body. */
+void or_potential_rows(int64_t n, const double *x, const double *m, int64_t n_r,
+                       const int32_t *rows, double *phi)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < n_r; ++r) {
+        const int64_t i = rows[r];
+        csum p = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i)
+                continue;
+            double dx = x[j] - x[i], dy = x[n + j] - x[n + i], dz = x[2 * n + j] - x[2 * n + i];
+            cs_add(&p, -m[j] / sqrt(dx * dx + dy * dy + dz * dz));
+        }
+        phi[r] = cs_get(&p);
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Adjoint of the regular force (no counterpart in the paper).                */
 /*   L = sum_b  w_a[:,b] . acc_b  +  w_j[:,b] . jerk_b                          */

@@ -285,6 +285,23 @@ def test_potential_two_body_and_plummer_energy():
     assert abs(T - 0.25) < 0.02
 
 
+def test_potential_rows_closed_forms():
+    """phi at selected bodies: a 3-4-5 triangle (exact distances 3, 4, 5) and
+    an equilateral triangle of side 2 (phi = -(sum of the other masses)/2)."""
+    x = np.array([[0.0, 3.0, 0.0], [0.0, 0.0, 4.0], [0.0, 0.0, 0.0]])
+    m = np.array([1.0, 0.5, 0.25])
+    phi = oracle.potential_rows(x, m, np.array([2, 0, 1], np.int32))
+    assert phi[0] == -(1.0 / 4 + 0.5 / 5)
+    assert phi[1] == -(0.5 / 3 + 0.25 / 4)
+    assert phi[2] == -(1.0 / 3 + 0.25 / 5)
+    h = math.sqrt(3.0)
+    x = np.array([[-1.0, 1.0, 0.0], [0.0, 0.0, h], [0.0, 0.0, 0.0]])
+    m = np.array([0.125, 0.25, 0.5])
+    phi = oracle.potential_rows(x, m, np.array([0, 1, 2], np.int32))
+    want = -np.array([0.75, 0.625, 0.375]) / 2.0
+    assert np.allclose(phi, want, rtol=4e-16, atol=0)
+
+
 # --------------------------------------------------------------------------- #
 # adjoint
 # --------------------------------------------------------------------------- #
