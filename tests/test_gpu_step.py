@@ -219,3 +219,41 @@ def test_hierarchical_block_steps_match_oracle(ctx):
     say(f"  T = {T}, max |dx| {dx:.2e}, max |dv| {dv:.2e}")
     assert dx <= 1e-11 and dv <= 1e-10
     assert np.array_equal(host(gt), ot)
+
+
+def test_step_kernels_bench_configuration(ctx):
+    """The rest of the block step as the benchmark runs it, at the 2^20 full
+    block of config 3: the irregular force over the lists of the full-block
+    regular pass (packed gathers) on 256 sampled rows, the corrector on all
+    2^20 entries bit for bit, and the potential at 256 sampled bodies."""
+    say("block-step kernels at the benchmark configuration")
+    s = W.config3()
+    t, t0, blk = W.config3_level(s, 3)
+    n, cap = s["n"], s["nb_cap"]
+    xp, vp, _ = nb.predict(dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(t0), t,
+                           ctx=ctx)
+    ox, ov = oracle.predict(t, s["x"], s["v"], s["a"], s["jk"], t0)
+    m = dev(s["m"])
+    reg = nb.regular_force(xp, vp, m, dev(blk), dev(s["rs2"][blk]), cap, "mixed", ctx=ctx)
+    irr = nb.irregular_force(xp, vp, m, dev(blk), cap, reg[2], reg[3], ctx=ctx)
+    rows = np.sort(np.random.default_rng(880).choice(n, 256, replace=False))
+    ra, rj, rc, rl, _, _ = oracle.regular(ox, ov, s["m"], blk[rows], s["rs2"][blk][rows], cap)
+    assert np.array_equal(host(reg[2])[rows], rc)
+    oa, oj = oracle.irregular(ox, ov, s["m"], blk[rows], cap, rc, rl)
+    ea, ej = row_rel_err(host(irr[0])[:, rows], oa), row_rel_err(host(irr[1])[:, rows], oj)
+    say(f"  irregular sampled err acc {ea.max():.2e} jerk {ej.max():.2e}")
+    assert ea.max() <= 1e-12 and ej.max() <= 1e-12
+    # corrector, every entry
+    h = np.full(n, 2.0 ** -10)
+    a1, j1 = host(reg[0]), host(reg[1])
+    got = nb.hermite_correct(dev(h), dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]),
+                             dev(a1), dev(j1), ctx=ctx)
+    ref = oracle.hermite_correct(h, s["x"], s["v"], s["a"], s["jk"], a1, j1)
+    for g, r in zip(got, ref):
+        assert np.array_equal(host(g), r)
+    # potential at sampled bodies
+    phi, _ = nb.potential(dev(s["x"]), m, ctx=ctx)
+    ophi = oracle.potential_rows(s["x"], s["m"], rows.astype(np.int32))
+    e = np.abs(host(phi)[rows] - ophi) / np.abs(ophi)
+    say(f"  potential sampled err {e.max():.2e}")
+    assert e.max() <= 1e-12
