@@ -153,15 +153,10 @@ extern "C" int nb_autotune(nb_ctx *ctx, int64_t n, const char *cache_path, int f
                 for (int rows : rows_opts) {
                     if (mapping == 1 && rows == 4) continue;
                     if (mapping == 2 && rows > ni) continue;
-                    const int64_t units = mapping == 1
-                                              ? (ni + rows * nb::kBlock - 1) / (rows * nb::kBlock)
-                                              : (ni + rows - 1) / rows * 1;
-                    const int64_t target = (int64_t)(ctx->cu_count > 0 ? ctx->cu_count : 256) *
-                                           (mapping == 1 ? 8 : 16);
-                    const int64_t base = std::max<int64_t>(1, (target + units - 1) / units);
+                    // the automatic split count of this mapping, halved and doubled
+                    const int64_t base = default_splits(ctx, n, ni, mapping, rows);
                     for (int64_t sc : {base / 2, base, base * 2}) {
-                        const int64_t maxs =
-                            std::max<int64_t>(1, n / (mapping == 1 ? 4 * nb::kTile : 4 * nb::kWave));
+                        const int64_t maxs = max_splits(n, mapping);
                         const int s = (int)std::max<int64_t>(1, std::min<int64_t>(sc, maxs));
                         nb::Plan p{mapping, rows, s};
                         bool dup = false;

@@ -21,36 +21,53 @@ int64_t bucket_log2(int64_t v)
     return b;
 }
 
-// Automatic plan for a block of n_i rows against n bodies.
+// Largest useful split count: at least 4 waves' worth of bodies per split in
+// the wave mapping, 8 tiles in the row-per-lane mapping.
+int64_t max_splits(int64_t n, int mapping)
+{
+    return std::max<int64_t>(1, n / (mapping == 2 ? 4 * nb::kWave : 8 * nb::kTile));
+}
+
+// Split count of the automatic plan for a given mapping and rows per lane
+// (or per wave).
+//  * mapping 2 (small blocks stream the j-set): about 2 waves per SIMD in
+//    total; more splits only add merge work (measured at N = 2^20,
+//    n_i = 1 .. 255).
+//  * mapping 1: many short work-groups even out their run-time differences;
+//    a split sweep over the step-level blocks at N = 2^20 was best near 64
+//    work-groups per CU in total (full block: 4 splits, +3-4%; 52428 rows:
+//    80 splits instead of 10, +25%).
+int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, int rows)
+{
+    const int64_t cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
+    int64_t units, target;
+    if (mapping == 2) {
+        units = (n_i + rows - 1) / rows;                       // row groups, one wave each
+        target = cus * 8;
+    } else {
+        units = (n_i + (int64_t)rows * nb::kBlock - 1) / ((int64_t)rows * nb::kBlock);
+        target = cus * 64;                                      // work-groups
+    }
+    const int64_t s = (target + std::max<int64_t>(units, 1) - 1) / std::max<int64_t>(units, 1);
+    return std::max<int64_t>(1, std::min(s, max_splits(n, mapping)));
+}
+
+// Automatic plan for a block of n_i rows against n bodies: the autotuned
+// entry for the size buckets if there is one, else the wave mapping for
+// n_i < 256 and one row per lane above.
 Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed)
 {
     auto it = ctx->tuned.find(std::make_tuple((int)mixed, bucket_log2(n), bucket_log2(n_i)));
     if (it != ctx->tuned.end()) return it->second;
     Plan p{};
-    const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
     if (n_i < 256) {
-        // small blocks stream the j-set: ~2 waves per SIMD in total; more
-        // splits only add merge work (measured at N = 2^20, n_i = 1 .. 255)
         p.mapping = 2;
         p.rows_per_lane = n_i >= 4 ? 4 : (n_i >= 2 ? 2 : 1);
-        const int64_t groups = (n_i + p.rows_per_lane - 1) / p.rows_per_lane;
-        const int64_t target = (int64_t)cus * 8;
-        int64_t s = (target + groups - 1) / groups;
-        const int64_t max_s = std::max<int64_t>(1, n / (4 * nb::kWave));
-        p.splits = (int)std::max<int64_t>(1, std::min(s, max_s));
     } else {
-        // many short work-groups even out their run-time differences: a
-        // split sweep over the step-level blocks at N = 2^20 was best near
-        // 64 work-groups per CU in total (full block: 4 splits, +3-4%;
-        // 52428 rows: 80 splits instead of 10, +25%)
         p.mapping = 1;
         p.rows_per_lane = 1;
-        const int64_t wgs = (n_i + p.rows_per_lane * nb::kBlock - 1) / (p.rows_per_lane * nb::kBlock);
-        const int64_t target = (int64_t)cus * 64;
-        int64_t s = (target + wgs - 1) / wgs;
-        const int64_t max_s = std::max<int64_t>(1, n / (8 * nb::kTile));   // >= 8 tiles a split
-        p.splits = (int)std::max<int64_t>(1, std::min(s, max_s));
     }
+    p.splits = (int)default_splits(ctx, n, n_i, p.mapping, p.rows_per_lane);
     return p;
 }
 

@@ -77,5 +77,7 @@ hipError_t timed_end(nb_ctx *ctx, int cls, hipEvent_t *ev);
 int64_t bucket_log2(int64_t v);
 double redo_k(const nb_ctx *ctx);
 nb::Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed);
+int64_t max_splits(int64_t n, int mapping);
+int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, int rows);
 void finish_plan(nb::Plan &p, int64_t n, int32_t n_i, int64_t *split_len);
 }  // namespace nbrt
