@@ -268,6 +268,16 @@ __global__ void fill_i32_kernel(int32_t *p, int32_t value, int64_t count)
     if (k < count) p[k] = value;
 }
 
+// Zeroes one or two words in a single launch (the overflow word and the
+// refinement counter of a force call).
+__global__ void clear_words_kernel(int32_t *a, int32_t *b)
+{
+    if (threadIdx.x == 0) {
+        *a = 0;
+        if (b) *b = 0;
+    }
+}
+
 }  // namespace
 
 static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
@@ -398,6 +408,12 @@ hipError_t launch_merge(bool mixed, const ForceArgs &a, hipStream_t s)
         dim3 grid((unsigned)((a.n_i + per - 1) / per));
         hipLaunchKernelGGL(merge_kernel, grid, dim3(kBlock), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_words(int32_t *a, int32_t *b, hipStream_t s)
+{
+    hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(64), 0, s, a, b);
     return hipGetLastError();
 }
 

@@ -103,6 +103,8 @@ hipError_t launch_predict(int64_t n, double t, const double *x, const double *v,
                           const double *m, double *xp, double *vp, float *m32,
                           hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t count, hipStream_t s);
+// Zeroes *a and, if b is not null, *b in one launch.
+hipError_t launch_clear_words(int32_t *a, int32_t *b, hipStream_t s);
 
 // Adjoint: two recompute passes.
 struct AdjointArgs {

@@ -284,9 +284,10 @@ int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
     if (n_i > 0 && nb_cap > 0 && !nb_list) return NB_ERR_INVALID_ARG;
     if (!ctx->usable) return NB_ERR_UNSUPPORTED;
 
-    hipError_t e = hipMemsetAsync(overflow, 0, sizeof(int32_t), ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e);
+    hipError_t e = hipSuccess;
     if (n_i == 0) {
+        e = nb::launch_clear_words(overflow, nullptr, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e);
         std::snprintf(ctx->last_plan, sizeof ctx->last_plan, "empty");
         return NB_OK;
     }
@@ -326,11 +327,10 @@ int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
         int rc = ensure_scratch(ctx, redo_bytes + slot_bytes);
         if (rc != NB_OK) return rc;
     }
-    if (redo_bytes) {
-        nb::bind_redo_scratch(fa, ctx->scratch, groups, n);
-        e = hipMemsetAsync(fa.redo_count, 0, sizeof(int32_t), ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e);
-    }
+    if (redo_bytes) nb::bind_redo_scratch(fa, ctx->scratch, groups, n);
+    // the overflow word and the refinement counter start at zero (one launch)
+    e = nb::launch_clear_words(overflow, redo_bytes ? fa.redo_count : nullptr, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e);
     nb::force_bind_scratch(fa, (char *)ctx->scratch + redo_bytes);
     std::snprintf(ctx->last_plan, sizeof ctx->last_plan,
                   "mapping=%d rows_per_lane=%d splits=%d split_len=%lld prec=%s", p.mapping,
