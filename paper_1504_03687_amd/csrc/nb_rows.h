@@ -5,7 +5,8 @@
 //
 // Slot layout of split partials (both launch kinds): a (row, split) pair owns
 // one slot; part[k * total_slots + slot] holds component k of its FP64 sums
-// (acc x,y,z, jerk x,y,z), seg_cnt[slot] its neighbour count and
+// (acc x,y,z, jerk x,y,z, then the mixed plan's two error-scale sums),
+// seg_cnt[slot] its neighbour count and
 // seg_list[slot * kSegCap ...] the first kSegCap neighbours in ascending j.
 #pragma once
 
