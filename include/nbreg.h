@@ -92,14 +92,15 @@ int nb_ctx_last_plan(nb_ctx *ctx, char *buf, int len);
 /* Upper bound on scratch bytes the context may hold (0 = no bound). */
 int nb_ctx_set_scratch_limit(nb_ctx *ctx, int64_t bytes);
 
-/* Kernel timing: when enabled, every launch of the library's force kernels is
- * bracketed by HIP events on the context's stream.  nb_ctx_kernel_time
- * synchronises those events and returns the summed milliseconds and the
- * launch count of one kernel class since the last reset (class 0 = regular
- * force main kernel, 1 = cross-split reduce, 2 = predictor, 3 = adjoint,
- * 4 = batched, 5 = mixed-precision FP64 refinement, 6 = irregular force,
- * corrector and potential, 7 = block-step scheduler, 8 = radius control: update,
- * compaction and scatter; the recomputed rows count under 0, 1, 5). */
+/* Kernel timing: when enabled, every launch (or launch sequence) of the
+ * library's kernels is bracketed by HIP events on the context's stream.
+ * nb_ctx_kernel_time synchronises those events and returns the summed
+ * milliseconds and the launch count of one kernel class since the last reset:
+ * 0 = regular force main kernel, 1 = cross-split reduce, 2 = predictor,
+ * 3 = adjoint, 4 = batched, 5 = mixed-precision FP64 refinement,
+ * 6 = irregular force (with its pack), corrector and potential,
+ * 7 = block-step scheduler, 8 = radius control (update, compaction and
+ * scatter; the recomputed rows count under 0, 1 and 5). */
 int nb_ctx_enable_timing(nb_ctx *ctx, int on);
 int nb_ctx_kernel_time(nb_ctx *ctx, int kernel_class, double *ms, int64_t *launches);
 int nb_ctx_reset_timing(nb_ctx *ctx);
@@ -207,7 +208,10 @@ int nb_autotune(nb_ctx *ctx, int64_t n, const char *cache_path, int flags);
  * acc, jerk: [3][n_i].  Entries outside [0, n) or equal to i are skipped and
  * set NB_STATUS_BAD_INDEX; a bad i_block entry gives a zero row.  With the
  * lists of a regular-force call on the same state, regular + irregular is the
- * full Newtonian force and jerk. */
+ * full Newtonian force and jerk.  For n_i >= n/128 the bodies are first
+ * packed into context scratch (64 B per body, one cache line per neighbour
+ * gather); the results are the same either way.  Errors: n <= 0 or
+ * n > INT32_MAX, n_i < 0, nb_cap < 0, NULL required pointer. */
 int nb_irregular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
                        const double *m, int32_t n_i, const int32_t *i_block, int32_t nb_cap,
                        const int32_t *nb_count, const int32_t *nb_list, double *acc,
@@ -221,7 +225,8 @@ int nb_irregular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *v
  *   a2 = (-6 (a0 - a1) - h (4 j0 + 2 j1)) / h^2 + h a3   (second derivative at
  *        the end of the step)
  * where a0, j0 are the force and jerk at the start of the step and a1, j1 at
- * its end (evaluated on the predicted state).  Outputs may alias x0 / v0. */
+ * its end (evaluated on the predicted state).  Outputs may alias x0 / v0.
+ * Errors: n <= 0 or n > INT32_MAX, NULL pointer. */
 int nb_hermite_correct(nb_ctx *ctx, int64_t n, const double *h, const double *x0,
                        const double *v0, const double *a0, const double *j0, const double *a1,
                        const double *j1, double *x1, double *v1, double *a2, double *a3);
@@ -229,7 +234,10 @@ int nb_hermite_correct(nb_ctx *ctx, int64_t n, const double *h, const double *x0
 /* Potential (section 3.2.1; used for the energy check and the scaling to
  * N-body units, section 3.3.2): phi[i] = -sum_{j != i} m_j / |x_j - x_i|
  * (x: [3][n] plane, FP64) and, if energy is not NULL, *energy (one device
- * double) = 1/2 sum_i m_i phi_i, reduced in a fixed order. */
+ * double) = 1/2 sum_i m_i phi_i, reduced in a fixed order.  1/|r| is the
+ * hardware estimate refined by one Newton step (relative error below 5e-15;
+ * the terms share one sign, so the sum keeps that bound).  Errors: n <= 0 or
+ * n > INT32_MAX, NULL x, m or phi. */
 int nb_potential(nb_ctx *ctx, int64_t n, const double *x, const double *m, double *phi,
                  double *energy);
 
