@@ -41,8 +41,8 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A)
         const BCluster C = A.clusters[I.cluster];
         const int64_t j0 = C.j_begin + (int64_t)I.split * C.split_len;
         const int64_t j1 = j0 + C.split_len < C.j_end ? j0 + C.split_len : C.j_end;
-        const Dest d{C.splits == 1, C.slot_base + (int64_t)I.split * C.n_rows,
-                     (int64_t)C.row_begin};
+        const Dest d{C.splits == 1, C.slot_base + (int64_t)I.split, (int64_t)C.row_begin,
+                     (int64_t)C.splits};
         rows_pass<MIXED, IR>(A.f, tile, I.row0, (int64_t)C.row_begin + C.n_rows, j0, j1, d,
                              C.near);
     }
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void batched_merge_kernel(BatchArgs A)
     if (q >= A.n_merge_rows) return;
     const int64_t b = A.merge_rows[q];
     const BCluster C = A.clusters[A.row_cluster[q]];
-    const MergeGeom g{C.splits, C.slot_base + (b - C.row_begin), (int64_t)C.n_rows, C.j_begin,
+    const MergeGeom g{C.splits, C.slot_base + (b - C.row_begin) * C.splits, 1, C.j_begin,
                       C.j_end, C.split_len};
     merge_row(A.f, b, g);
 }

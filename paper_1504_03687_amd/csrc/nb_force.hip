@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void force_rows_kernel(ForceArgs a)
     const int32_t split = blockIdx.y;
     const int64_t j0 = (int64_t)split * a.split_len;
     const int64_t j1 = j0 + a.split_len < a.n ? j0 + a.split_len : a.n;
-    const Dest d{a.splits == 1, (int64_t)split * a.n_i, 0};
+    const Dest d{a.splits == 1, (int64_t)split, 0, (int64_t)a.splits};
     rows_pass<MIXED, IR>(a, tile, (int64_t)blockIdx.x * IR * kBlock, a.n_i, j0, j1, d,
                          a.near_factor);
 }
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
     const int32_t split = (int32_t)(gw - group * a.splits);
     const int64_t j0 = (int64_t)split * a.split_len;
     const int64_t j1 = j0 + a.split_len < a.n ? j0 + a.split_len : a.n;
-    const Dest d{a.splits == 1, (int64_t)split * a.n_i, 0};
+    const Dest d{a.splits == 1, (int64_t)split, 0, (int64_t)a.splits};
 
     // Row data is uniform across the wave (scalar loads, scalar registers).
     double rx[G], ry[G], rz[G], rvx[G], rvy[G], rvz[G], hi[G];
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(ForceArgs a)
     const int64_t b = (int64_t)blockIdx.x * (kBlock / kWave) +
                       __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (b >= a.n_i) return;
-    const MergeGeom g{a.splits, b, a.n_i, 0, a.n, a.split_len};
+    const MergeGeom g{a.splits, b * a.splits, 1, 0, a.n, a.split_len};
     merge_row(a, b, g);
 }
 
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void merge_wg_kernel(ForceArgs a)
     __shared__ double lds[kBlock / kWave];
     __shared__ int64_t scan[kBlock];
     const int64_t b = blockIdx.x;
-    const MergeGeom g{a.splits, b, a.n_i, 0, a.n, a.split_len};
+    const MergeGeom g{a.splits, b * a.splits, 1, 0, a.n, a.split_len};
     merge_row_wg(a, b, g, lds, scan);
 }
 

@@ -46,8 +46,8 @@ struct ForceArgs {
     // split layout: split s covers j in [s * split_len, min(n, (s+1) * split_len))
     int32_t splits;
     int64_t split_len;
-    // scratch (splits > 1): one slot per (row, split), slot = split * n_i + b;
-    // part [kSlotComp][total_slots], seg_cnt [total_slots],
+    // scratch (splits > 1): one slot per (row, split), slot = b * splits + split;
+    // part [total_slots][kSlotComp], seg_cnt [total_slots],
     // seg_list [total_slots][kSegCap]
     int64_t total_slots;
     double *part;

@@ -4,10 +4,13 @@
 // (nb_batched.hip).
 //
 // Slot layout of split partials (both launch kinds): a (row, split) pair owns
-// one slot; part[k * total_slots + slot] holds component k of its FP64 sums
-// (acc x,y,z, jerk x,y,z, then the mixed plan's two error-scale sums),
-// seg_cnt[slot] its neighbour count and
+// one slot, and a row's slots are consecutive (slot = row's first slot +
+// split).  part[slot * kSlotComp + k] holds component k of its FP64 sums
+// (acc x,y,z, jerk x,y,z, then the mixed plan's two error-scale sums: one
+// 64-byte record per slot), seg_cnt[slot] its neighbour count and
 // seg_list[slot * kSegCap ...] the first kSegCap neighbours in ascending j.
+// The force kernels write whole records; the merge reads a row's records as
+// one contiguous run.
 #pragma once
 
 #include "nb_internal.h"
@@ -36,16 +39,24 @@ struct Row {
 };
 
 // Where the rows of one pass write: straight to the caller's outputs, or to
-// the slots of one split (slot of row b = slot_base + b - row_origin).
+// the slots of one split (slot of row b = slot_base + (b - row_origin) *
+// slot_stride, where slot_stride is the split count).
 struct Dest {
     bool direct;
     int64_t slot_base;
     int64_t row_origin;
+    int64_t slot_stride;
 };
 
 __device__ __forceinline__ int64_t dest_slot(const Dest &d, int64_t b)
 {
-    return d.slot_base + (b - d.row_origin);
+    return d.slot_base + (b - d.row_origin) * d.slot_stride;
+}
+
+// The 64-byte partial-sum record of one slot.
+__device__ __forceinline__ double2 *slot_rec(const ForceArgs &a, int64_t slot)
+{
+    return reinterpret_cast<double2 *>(a.part + slot * kSlotComp);
 }
 
 template <bool MIXED>
@@ -224,16 +235,11 @@ __device__ __forceinline__ void row_store(const ForceArgs &a, int64_t b, const D
             redo_push(a, b, j0, j1);
     } else {
         const int64_t slot = dest_slot(d, b);
-        double *p = a.part + slot;
-        const int64_t T = a.total_slots;
-        p[0] = S.ax;
-        p[T] = S.ay;
-        p[2 * T] = S.az;
-        p[3 * T] = S.jx;
-        p[4 * T] = S.jy;
-        p[5 * T] = S.jz;
-        p[6 * T] = S.va;
-        p[7 * T] = S.vj;
+        double2 *p = slot_rec(a, slot);
+        p[0] = make_double2(S.ax, S.ay);
+        p[1] = make_double2(S.az, S.jx);
+        p[2] = make_double2(S.jy, S.jz);
+        p[3] = make_double2(S.va, S.vj);
         a.seg_cnt[slot] = cnt;
     }
 }
@@ -331,13 +337,16 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
     const int64_t i = a.i_block[b];
     const bool bad = i < 0 || i >= a.n;
     const int32_t S = g.splits;
-    const int64_t T = a.total_slots;
 
     double v[kSlotComp] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int32_t s = lane; s < S; s += kWave) {
-        const double *p = a.part + g.slot0 + (int64_t)s * g.slot_step;
+        const double2 *p = slot_rec(a, g.slot0 + (int64_t)s * g.slot_step);
 #pragma unroll
-        for (int k = 0; k < kSlotComp; ++k) v[k] += p[(int64_t)k * T];
+        for (int k = 0; k < kSlotComp / 2; ++k) {
+            const double2 t = p[k];
+            v[2 * k] += t.x;
+            v[2 * k + 1] += t.y;
+        }
     }
 #pragma unroll
     for (int k = 0; k < kSlotComp; ++k) v[k] = wave_sum(v[k]);
@@ -490,7 +499,6 @@ __device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, cons
     const int64_t i = a.i_block[b];
     const bool bad = i < 0 || i >= a.n;
     const int32_t S = g.splits;
-    const int64_t T = a.total_slots;
     const int32_t K = (S + kBlock - 1) / kBlock;
     const int32_t s0 = tid * K;
     const int32_t s1 = s0 + K < S ? s0 + K : S;
@@ -504,9 +512,13 @@ __device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, cons
 #pragma unroll
         for (int u = 0; u < kMergeBatch; ++u) {
             const int32_t s = sb + u * kBlock;
-            const int64_t slot = g.slot0 + (int64_t)(s < S ? s : 0) * g.slot_step;
+            const double2 *p = slot_rec(a, g.slot0 + (int64_t)(s < S ? s : 0) * g.slot_step);
 #pragma unroll
-            for (int k = 0; k < kSlotComp; ++k) t[u][k] = a.part[(int64_t)k * T + slot];
+            for (int k = 0; k < kSlotComp / 2; ++k) {
+                const double2 q = p[k];
+                t[u][2 * k] = q.x;
+                t[u][2 * k + 1] = q.y;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kMergeBatch; ++u)
