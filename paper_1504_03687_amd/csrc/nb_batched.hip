@@ -48,16 +48,25 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A)
     }
 }
 
+// W lanes per merged row (W = merge_width of the largest split count among
+// the split clusters), kBlock / W rows per work-group.
+template <int W>
 __global__ __launch_bounds__(kBlock) void batched_merge_kernel(BatchArgs A)
 {
-    const int64_t q = (int64_t)blockIdx.x * (kBlock / kWave) +
-                      __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    if (q >= A.n_merge_rows) return;
-    const int64_t b = A.merge_rows[q];
-    const BCluster C = A.clusters[A.row_cluster[q]];
-    const MergeGeom g{C.splits, C.slot_base + (b - C.row_begin) * C.splits, 1, C.j_begin,
+    const int64_t wave_q0 = (int64_t)blockIdx.x * (kBlock / W) +
+                            __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * (kWave / W);
+    if (wave_q0 >= A.n_merge_rows) return;   // whole wave past the last row
+    const int64_t q = (int64_t)blockIdx.x * (kBlock / W) + threadIdx.x / W;
+    const bool has = q < A.n_merge_rows;
+    int64_t b = 0;
+    MergeGeom g{0, 0, 1, 0, 0, 0};
+    if (has) {
+        b = A.merge_rows[q];
+        const BCluster C = A.clusters[A.row_cluster[q]];
+        g = MergeGeom{C.splits, C.slot_base + (b - C.row_begin) * C.splits, 1, C.j_begin,
                       C.j_end, C.split_len};
-    merge_row(A.f, b, g);
+    }
+    merge_row<W>(A.f, b, has, g);
 }
 
 template <bool MIXED, int IR>
@@ -100,9 +109,14 @@ hipError_t launch_batched(bool mixed, int rows_per_lane, int grid, const BatchAr
 hipError_t launch_batched_merge(const BatchArgs &a, hipStream_t s)
 {
     if (a.n_merge_rows <= 0) return hipSuccess;
-    const int per = kBlock / kWave;
-    hipLaunchKernelGGL(batched_merge_kernel, dim3((unsigned)((a.n_merge_rows + per - 1) / per)),
-                       dim3(kBlock), 0, s, a);
+    const int w = merge_width(a.max_splits);
+    const dim3 grid((unsigned)((a.n_merge_rows + kBlock / w - 1) / (kBlock / w)));
+    if (w == 4)
+        hipLaunchKernelGGL(batched_merge_kernel<4>, grid, dim3(kBlock), 0, s, a);
+    else if (w == 16)
+        hipLaunchKernelGGL(batched_merge_kernel<16>, grid, dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(batched_merge_kernel<64>, grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -284,6 +298,8 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     A.merge_rows = dmr;
     A.row_cluster = drc;
     A.n_merge_rows = (int32_t)merge_rows.size();
+    A.max_splits = 1;
+    for (int32_t k = 0; k < C; ++k) A.max_splits = std::max(A.max_splits, cl[(size_t)k].splits);
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
     c->grid = cus * nb::batched_max_blocks_per_cu(mixed, c->rows_per_lane);
     if (A.n_items < c->grid) c->grid = std::max(1, A.n_items);

@@ -184,14 +184,16 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
     flush_flags(a, ovf, bad, nonfin);
 }
 
-// One wave per row.
+// W lanes per row (W = merge_width(splits)), kBlock / W rows per work-group.
+template <int W>
 __global__ __launch_bounds__(kBlock) void merge_kernel(ForceArgs a)
 {
-    const int64_t b = (int64_t)blockIdx.x * (kBlock / kWave) +
-                      __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    if (b >= a.n_i) return;
+    const int64_t wave_row0 = (int64_t)blockIdx.x * (kBlock / W) +
+                              __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * (kWave / W);
+    if (wave_row0 >= a.n_i) return;   // whole wave past the last row
+    const int64_t b = (int64_t)blockIdx.x * (kBlock / W) + threadIdx.x / W;
     const MergeGeom g{a.splits, b * a.splits, 1, 0, a.n, a.split_len};
-    merge_row(a, b, g);
+    merge_row<W>(a, b, b < a.n_i, g);
 }
 
 // One work-group per row for plans with many splits.
@@ -404,9 +406,15 @@ hipError_t launch_merge(bool mixed, const ForceArgs &a, hipStream_t s)
     if (a.splits >= 256) {   // few rows, many splits: one work-group per row
         hipLaunchKernelGGL(merge_wg_kernel, dim3((unsigned)a.n_i), dim3(kBlock), 0, s, a);
     } else {
-        const int per = kBlock / kWave;
+        const int w = merge_width(a.splits);
+        const int per = kBlock / w;
         dim3 grid((unsigned)((a.n_i + per - 1) / per));
-        hipLaunchKernelGGL(merge_kernel, grid, dim3(kBlock), 0, s, a);
+        if (w == 4)
+            hipLaunchKernelGGL(merge_kernel<4>, grid, dim3(kBlock), 0, s, a);
+        else if (w == 16)
+            hipLaunchKernelGGL(merge_kernel<16>, grid, dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL(merge_kernel<64>, grid, dim3(kBlock), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -147,6 +147,7 @@ struct BatchArgs {
     const int32_t *merge_rows;   // rows of clusters with splits > 1
     const int32_t *row_cluster;  // cluster of each merge row
     int32_t n_merge_rows;
+    int32_t max_splits;          // largest split count of any cluster
 };
 hipError_t launch_batched(bool mixed, int rows_per_lane, int grid, const BatchArgs &a,
                           hipStream_t s);

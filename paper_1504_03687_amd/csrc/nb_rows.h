@@ -327,19 +327,46 @@ struct MergeGeom {
     int64_t j_begin, j_end, split_len;
 };
 
-// Merge of one row by one whole wave: sums the split partials in a fixed
-// order, concatenates neighbour segments in split order (ascending j), writes
-// the true count, and rebuilds any segment that overflowed its scratch
-// capacity by re-running the canonical test over that split's j-range.
-__device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const MergeGeom &g)
+// Sum over the W aligned lanes of a lane group (butterfly, largest offset
+// first; every lane of the group gets the result).
+template <int W>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Lanes per row of the single-wave merge for a given split count: the next of
+// 4, 16, 64 at or above it.  For S <= W each lane holds at most one partial
+// and the lanes past S hold exact zeros, which the butterfly adds before any
+// two partials meet, so every W >= S gives the same bits (and the same as one
+// whole wave per row).
+__host__ __device__ constexpr int merge_width(int64_t splits)
+{
+    return splits <= 4 ? 4 : (splits <= 16 ? 16 : 64);
+}
+
+// Merge of one row by a group of W lanes (W = 64: one whole wave; smaller W:
+// 64/W rows per wave): sums the split partials in a fixed order, concatenates
+// neighbour segments in split order (ascending j), writes the true count, and
+// rebuilds any segment that overflowed its scratch capacity by re-running the
+// canonical test over that split's j-range.  has_row = false for a group past
+// the last row; every lane of the wave must call this (it ends in a ballot).
+template <int W>
+__device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, bool has_row,
+                                          const MergeGeom &g)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t i = a.i_block[b];
-    const bool bad = i < 0 || i >= a.n;
-    const int32_t S = g.splits;
+    const int l = lane & (W - 1);       // lane within the row's group
+    const int gbase = lane - l;         // first lane of the group
+    const uint64_t gmask = W == kWave ? ~0ull : (((1ull << W) - 1) << gbase);
+    const int64_t i = has_row ? a.i_block[b] : -1;
+    const bool bad = has_row && (i < 0 || i >= a.n);
+    const int32_t S = has_row ? g.splits : 0;
 
     double v[kSlotComp] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int32_t s = lane; s < S; s += kWave) {
+    for (int32_t s = l; s < S; s += W) {
         const double2 *p = slot_rec(a, g.slot0 + (int64_t)s * g.slot_step);
 #pragma unroll
         for (int k = 0; k < kSlotComp / 2; ++k) {
@@ -349,37 +376,37 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
         }
     }
 #pragma unroll
-    for (int k = 0; k < kSlotComp; ++k) v[k] = wave_sum(v[k]);
+    for (int k = 0; k < kSlotComp; ++k) v[k] = group_sum<W>(v[k]);
 
     bool ovf = false, nonfin = false;
     if (bad) {
-        if (lane == 0) {
+        if (l == 0) {
             for (int k = 0; k < 3; ++k) {
                 a.acc[(int64_t)k * a.n_i + b] = 0.0;
                 a.jerk[(int64_t)k * a.n_i + b] = 0.0;
             }
             a.nb_count[b] = 0;
         }
-    } else {
+    } else if (has_row) {
         const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
         const float rs2f = (float)a.rs2[b];
-        int64_t off = 0;   // uniform: neighbours placed so far (true count)
-        for (int32_t s0 = 0; s0 < S; s0 += kWave) {
-            const int32_t s = s0 + lane;
+        int64_t off = 0;   // uniform in the group: neighbours placed so far (true count)
+        for (int32_t s0 = 0; s0 < S; s0 += W) {
+            const int32_t s = s0 + l;
             const int64_t slot = g.slot0 + (int64_t)s * g.slot_step;
             const int32_t c = s < S ? a.seg_cnt[slot] : 0;
-            int64_t inc = c;   // inclusive scan of c over lanes
+            int64_t inc = c;   // inclusive scan of c over the group
 #pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int64_t t = __shfl_up(inc, o, kWave);
-                if (lane >= o) inc += t;
+            for (int o = 1; o < W; o <<= 1) {
+                const int64_t t = __shfl_up(inc, o, W);
+                if (l >= o) inc += t;
             }
             const int64_t start = off + inc - c;
             const bool room = c > 0 && start < a.cap;
             const bool rebuild = room && c > kSegCap;
-            // segments that fit: the whole wave copies each one (coalesced)
+            // segments that fit: the whole group copies each one (coalesced)
             const int64_t take = room ? ((int64_t)c < a.cap - start ? c : a.cap - start) : 0;
-            uint64_t cp = __ballot(room && !rebuild);
+            uint64_t cp = __ballot(room && !rebuild) & gmask;
             while (cp) {
                 const int q = __builtin_ctzll(cp);
                 cp &= cp - 1;
@@ -388,10 +415,10 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
                 const int64_t tk = __shfl(take, q, kWave);
                 const int32_t *src = a.seg_list + sl * kSegCap;
                 int32_t *dst = a.nb_list + b * (int64_t)a.cap + st;
-                for (int64_t e = lane; e < tk; e += kWave) dst[e] = src[e];
+                for (int64_t e = l; e < tk; e += W) dst[e] = src[e];
             }
-            uint64_t rb = __ballot(rebuild);
-            while (rb) {   // overflowed segments: the wave rescans them one by one
+            uint64_t rb = __ballot(rebuild) & gmask;
+            while (rb) {   // overflowed segments: the group rescans them one by one
                 const int q = __builtin_ctzll(rb);
                 rb &= rb - 1;
                 const int32_t sq = __shfl(s, q, kWave);
@@ -400,15 +427,15 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
                 const int64_t jb = g.j_begin + (int64_t)sq * g.split_len;
                 const int64_t je = jb + g.split_len < g.j_end ? jb + g.split_len : g.j_end;
                 int64_t placed = 0;
-                for (int64_t base = jb; base < je && placed < lim; base += kWave) {
-                    const int64_t j = base + lane;
+                for (int64_t base = jb; base < je && placed < lim; base += W) {
+                    const int64_t j = base + l;
                     bool nbr = false;
                     if (j < je && j != i) {
                         const double dx = a.xp[j] - xi, dy = a.xp[a.n + j] - yi,
                                      dz = a.xp[2 * a.n + j] - zi;
                         nbr = canon_r2f(dx, dy, dz) < rs2f;
                     }
-                    const uint64_t nm = __ballot(nbr);
+                    const uint64_t nm = __ballot(nbr) & gmask;
                     if (nbr) {
                         const int64_t p = placed + lanes_below(nm);
                         if (p < lim) a.nb_list[b * (int64_t)a.cap + st + p] = (int32_t)j;
@@ -416,9 +443,9 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
                     placed += __popcll(nm);
                 }
             }
-            off += __shfl(inc, kWave - 1, kWave);
+            off += __shfl(inc, gbase + W - 1, kWave);
         }
-        if (lane == 0) {
+        if (l == 0) {
             a.acc[b] = v[0];
             a.acc[a.n_i + b] = v[1];
             a.acc[2 * (int64_t)a.n_i + b] = v[2];
@@ -432,7 +459,7 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, const M
                 redo_push(a, b, g.j_begin, g.j_end);
         }
     }
-    flush_flags(a, ovf, bad && lane == 0, nonfin);
+    flush_flags(a, ovf, bad && l == 0, nonfin);
 }
 
 // Fixed-order sum of one value over the 256 lanes of a work-group (all
