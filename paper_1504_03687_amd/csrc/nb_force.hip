@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(ForceArgs a)
 // One work-group per row for plans with many splits.
 __global__ __launch_bounds__(kBlock) void merge_wg_kernel(ForceArgs a)
 {
-    __shared__ double lds[kBlock / kWave];
+    __shared__ double lds[kSlotComp][kBlock / kWave];
     __shared__ int64_t scan[kBlock];
     const int64_t b = blockIdx.x;
     const MergeGeom g{a.splits, b * a.splits, 1, 0, a.n, a.split_len};
@@ -219,9 +219,11 @@ __device__ __forceinline__ void write_forces(const ForceArgs &a, int64_t b, cons
 // Refinement, pass 1: the first redo_rcap listed rows as (row, chunk) items
 // over the whole grid (chunk partials to scratch); any further rows one
 // work-group each, chunks in order.  Both give the same chunk-ordered sum.
+// Items past a row's own chunk count (rows shorter than the longest j-range
+// of the call) are skipped before any row data is read.
 __global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
 {
-    __shared__ double lds[kBlock / kWave];
+    __shared__ double lds[6][kBlock / kWave];
     const int32_t count = __builtin_amdgcn_readfirstlane(*(volatile int32_t *)a.redo_count);
     const int32_t par = count < a.redo_rcap ? count : a.redo_rcap;
     const int32_t C = a.redo_chunks;
@@ -231,6 +233,7 @@ __global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
     // of bodies (L2 reuse across the refined rows)
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const int32_t c = (int32_t)(it / par), q = (int32_t)(it % par);
+        if (c >= redo_row_chunks(a, q)) continue;   // uniform over the work-group
         redo_chunk(a, q, c, lds, v);
         if (threadIdx.x == 0)
 #pragma unroll
@@ -238,7 +241,8 @@ __global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
     }
     for (int64_t q = (int64_t)par + blockIdx.x; q < count; q += gridDim.x) {
         double acc[6] = {0, 0, 0, 0, 0, 0};
-        for (int32_t c = 0; c < C; ++c) {
+        const int32_t nc = redo_row_chunks(a, (int32_t)q);
+        for (int32_t c = 0; c < nc; ++c) {
             redo_chunk(a, (int32_t)q, c, lds, v);
 #pragma unroll
             for (int k = 0; k < 6; ++k) acc[k] += v[k];
@@ -257,7 +261,8 @@ __global__ __launch_bounds__(256) void redo_final_kernel(ForceArgs a)
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < par;
          q += (int64_t)gridDim.x * blockDim.x) {
         double v[6] = {0, 0, 0, 0, 0, 0};
-        for (int32_t c = 0; c < C; ++c)
+        const int32_t nc = redo_row_chunks(a, (int32_t)q);
+        for (int32_t c = 0; c < nc; ++c)
 #pragma unroll
             for (int k = 0; k < 6; ++k) v[k] += a.redo_part[(q * C + c) * 6 + k];
         write_forces(a, a.redo_rows[q], v);

@@ -462,26 +462,41 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, bool ha
     flush_flags(a, ovf, bad && l == 0, nonfin);
 }
 
-// Fixed-order sum of one value over the 256 lanes of a work-group (all
-// lanes must call it); every lane gets the result.
-__device__ __forceinline__ double block_sum(double v, double *lds /* [kBlock / kWave] */)
+// Fixed-order sums of K values over the 256 lanes of a work-group (all lanes
+// must call it): each value is summed over its wave by a butterfly, then the
+// four wave sums are added in wave order; every lane gets the results.
+template <int K>
+__device__ __forceinline__ void block_sums(double v[K], double (*lds)[kBlock / kWave])
 {
-    v = wave_sum(v);
-    const int w = threadIdx.x / kWave;
-    __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
-    __syncthreads();
-    double t = 0.0;
 #pragma unroll
-    for (int k = 0; k < kBlock / kWave; ++k) t += lds[k];
-    return t;
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();   // earlier readers of lds are done
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[k][w] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kBlock / kWave; ++q) t += lds[k][q];
+        v[k] = t;
+    }
 }
 
-// FP64 sums over one fixed chunk [j0 + c*kRedoChunk, ...) of a refined row's
-// j-range, by a whole work-group in a fixed pattern; every lane returns the
-// six sums (acc, jerk).  Chunks past the row's range are empty (zero).
-__device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_t c, double *lds,
-                                          double out[6])
+// Chunks of refined row q: its j-range cut into kRedoChunk bodies.
+__device__ __forceinline__ int32_t redo_row_chunks(const ForceArgs &a, int32_t q)
+{
+    const int64_t len = (int64_t)a.redo_j1[q] - a.redo_j0[q];
+    return len > 0 ? (int32_t)((len + kRedoChunk - 1) / kRedoChunk) : 0;
+}
+
+// FP64 sums over chunk c [j0 + c*kRedoChunk, ...) of refined row q, by a whole
+// work-group in a fixed pattern; every lane gets the six sums (acc, jerk).
+// The chunk must lie inside the row's j-range (c < redo_row_chunks).
+__device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_t c,
+                                          double (*lds)[kBlock / kWave], double out[6])
 {
     const int64_t b = a.redo_rows[q];
     const int64_t j0 = a.redo_j0[q], j1 = a.redo_j1[q];
@@ -507,9 +522,13 @@ __device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_
         }
         accum_f64(S, dx, dy, dz, r2, J.vx - vxi, J.vy - vyi, J.vz - vzi, J.m, excl);
     }
-    const double v[6] = {S.ax, S.ay, S.az, S.jx, S.jy, S.jz};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) out[k] = block_sum(v[k], lds);
+    out[0] = S.ax;
+    out[1] = S.ay;
+    out[2] = S.az;
+    out[3] = S.jx;
+    out[4] = S.jy;
+    out[5] = S.jz;
+    block_sums<6>(out, lds);
 }
 
 constexpr int kMergeBatch = 8;    // strides of split partials loaded per batch
@@ -520,7 +539,7 @@ constexpr int kCountBatch = 16;   // segment counts loaded per batch
 // owns the contiguous splits [t*K, (t+1)*K) and a work-group prefix scan of
 // the lanes' counts places its segments, so the list stays in split order.
 __device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, const MergeGeom &g,
-                                             double *lds, int64_t *scan)
+                                             double (*lds)[kBlock / kWave], int64_t *scan)
 {
     const int tid = threadIdx.x;
     const int64_t i = a.i_block[b];
@@ -573,8 +592,7 @@ __device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, cons
                 if (c[u] > 0 && sb + u - s0 < 64) nz |= 1ull << (sb + u - s0);
             }
     }
-#pragma unroll
-    for (int k = 0; k < kSlotComp; ++k) v[k] = block_sum(v[k], lds);
+    block_sums<kSlotComp>(v, lds);
 
     // exclusive scan of the lanes' neighbour counts (Hillis-Steele in LDS)
     __syncthreads();
