@@ -216,28 +216,47 @@ __device__ __forceinline__ void write_forces(const ForceArgs &a, int64_t b, cons
     a.jerk[2 * (int64_t)a.n_i + b] = v[5];
 }
 
-// Refinement, pass 1: the first redo_rcap listed rows as (row, chunk) items
-// over the whole grid (chunk partials to scratch); any further rows one
+// Refinement, pass 1: the first redo_rcap listed rows as (row group, chunk)
+// items over the whole grid (chunk partials to scratch); any further rows one
 // work-group each, chunks in order.  Both give the same chunk-ordered sum.
-// Items past a row's own chunk count (rows shorter than the longest j-range
-// of the call) are skipped before any row data is read.
+// A group is kRedoRows consecutive listed rows: when they share one j-range
+// (always in a single-block call) they are summed together, each body loaded
+// once; otherwise row by row.  Chunks past a row's own range are skipped.
 __global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
 {
-    __shared__ double lds[6][kBlock / kWave];
+    __shared__ double lds[kRedoRows * 6][kBlock / kWave];
     const int32_t count = __builtin_amdgcn_readfirstlane(*(volatile int32_t *)a.redo_count);
     const int32_t par = count < a.redo_rcap ? count : a.redo_rcap;
     const int32_t C = a.redo_chunks;
-    const int64_t items = (int64_t)par * C;
-    double v[6];
+    const int32_t G = (par + kRedoRows - 1) / kRedoRows;
+    const int64_t items = (int64_t)G * C;
+    double v[kRedoRows * 6];
     // chunk-major order: work-groups running at the same time share a chunk
     // of bodies (L2 reuse across the refined rows)
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const int32_t c = (int32_t)(it / par), q = (int32_t)(it % par);
-        if (c >= redo_row_chunks(a, q)) continue;   // uniform over the work-group
-        redo_chunk(a, q, c, lds, v);
-        if (threadIdx.x == 0)
+        const int32_t c = (int32_t)(it / G), q0 = (int32_t)(it % G) * kRedoRows;
+        const int nr = par - q0 < kRedoRows ? par - q0 : kRedoRows;
+        bool same = true;   // uniform over the work-group
+        for (int r = 1; r < nr; ++r)
+            same = same && a.redo_j0[q0 + r] == a.redo_j0[q0] && a.redo_j1[q0 + r] == a.redo_j1[q0];
+        if (same) {
+            if (c >= redo_row_chunks(a, q0)) continue;
+            redo_chunk_rows(a, q0, nr, c, lds, v);
+            if (threadIdx.x == 0)
+                for (int r = 0; r < nr; ++r)
 #pragma unroll
-            for (int k = 0; k < 6; ++k) a.redo_part[((int64_t)q * C + c) * 6 + k] = v[k];
+                    for (int k = 0; k < 6; ++k)
+                        a.redo_part[((int64_t)(q0 + r) * C + c) * 6 + k] = v[r * 6 + k];
+        } else {
+            for (int r = 0; r < nr; ++r) {
+                const int32_t q = q0 + r;
+                if (c >= redo_row_chunks(a, q)) continue;
+                redo_chunk(a, q, c, lds, v);
+                if (threadIdx.x == 0)
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) a.redo_part[((int64_t)q * C + c) * 6 + k] = v[k];
+            }
+        }
     }
     for (int64_t q = (int64_t)par + blockIdx.x; q < count; q += gridDim.x) {
         double acc[6] = {0, 0, 0, 0, 0, 0};

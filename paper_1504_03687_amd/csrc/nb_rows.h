@@ -531,6 +531,71 @@ __device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_
     block_sums<6>(out, lds);
 }
 
+// Refined rows sharing one j-range are summed kRedoRows at a time: each lane
+// loads a body once for all of them.  Per row the lane order and the
+// reduction are those of redo_chunk, so every row gets the same bits.
+constexpr int kRedoRows = 2;
+
+// Chunk c of refined rows q0 .. q0+nr-1 (nr <= kRedoRows), which all have
+// the j-range of row q0 and c < its chunk count; out[r][k] for row q0 + r.
+__device__ __forceinline__ void redo_chunk_rows(const ForceArgs &a, int32_t q0, int nr, int32_t c,
+                                               double (*lds)[kBlock / kWave],
+                                               double out[kRedoRows * 6])
+{
+    const int64_t j0 = a.redo_j0[q0], j1 = a.redo_j1[q0];
+    const int64_t cj0 = j0 + (int64_t)c * kRedoChunk;
+    const int64_t cj1 = cj0 + kRedoChunk < j1 ? cj0 + kRedoChunk : j1;
+    double xi[kRedoRows], yi[kRedoRows], zi[kRedoRows], vxi[kRedoRows], vyi[kRedoRows],
+        vzi[kRedoRows], hi[kRedoRows];
+    float rs2f[kRedoRows];
+    int64_t ii[kRedoRows];
+    Sums<false> S[kRedoRows];
+#pragma unroll
+    for (int r = 0; r < kRedoRows; ++r) {
+        S[r].zero();
+        const int32_t q = q0 + (r < nr ? r : 0);
+        const int64_t b = a.redo_rows[q];
+        const int64_t i = a.i_block[b];
+        ii[r] = i;
+        xi[r] = a.xp[i];
+        yi[r] = a.xp[a.n + i];
+        zi[r] = a.xp[2 * a.n + i];
+        vxi[r] = a.vp[i];
+        vyi[r] = a.vp[a.n + i];
+        vzi[r] = a.vp[2 * a.n + i];
+        rs2f[r] = (float)a.rs2[b];
+        hi[r] = cand_bound_f64(rs2f[r]);
+    }
+    for (int64_t j = cj0 + threadIdx.x; j < cj1; j += kBlock) {
+        JBody J;
+        load_body(J, a, j, cj1);
+#pragma unroll
+        for (int r = 0; r < kRedoRows; ++r) {
+            if (r >= nr) break;
+            const double dx = J.x - xi[r], dy = J.y - yi[r], dz = J.z - zi[r];
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            bool excl = false;
+            if (r2 < hi[r]) {
+                double ex = dx, ey = dy, ez = dz;
+                opaque(ex, ey, ez);
+                excl = j == ii[r] || canon_r2f(ex, ey, ez) < rs2f[r];
+            }
+            accum_f64(S[r], dx, dy, dz, r2, J.vx - vxi[r], J.vy - vyi[r], J.vz - vzi[r], J.m,
+                      excl);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kRedoRows; ++r) {
+        out[r * 6 + 0] = S[r].ax;
+        out[r * 6 + 1] = S[r].ay;
+        out[r * 6 + 2] = S[r].az;
+        out[r * 6 + 3] = S[r].jx;
+        out[r * 6 + 4] = S[r].jy;
+        out[r * 6 + 5] = S[r].jz;
+    }
+    block_sums<kRedoRows * 6>(out, lds);
+}
+
 constexpr int kMergeBatch = 8;    // strides of split partials loaded per batch
 constexpr int kCountBatch = 16;   // segment counts loaded per batch
 
