@@ -98,6 +98,31 @@ def test_plans_ragged(ctx, plan, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_merge_group_widths(ctx, prec):
+    """Split counts on both sides of the merge's lane-group widths (4, 16 and
+    64 lanes per row, and more splits than lanes), a ragged block of 777 rows
+    (partial groups and waves) and a cap small enough to truncate lists."""
+    n = 17308   # 68 tiles of 256: the requests below land on distinct counts
+    s = W.small_state(41, n, k_nn=40)
+    rng = np.random.default_rng(41)
+    ib = rng.integers(0, n, 777).astype(np.int32)
+    rs2 = s["rs2"][ib].copy()
+    seen = set()
+    try:
+        for req in (2, 4, 5, 16, 17, 64, 68):
+            ctx.set_plan(1, 1, req)
+            say(f"merge widths {prec} splits requested {req}")
+            for cap in (64, 8):
+                res = nb.regular_force(dev(s["x"]), dev(s["v"]), dev(s["m"]), dev(ib), dev(rs2),
+                                       cap, prec, ctx=ctx)
+                compare_force(res, s["x"], s["v"], s["m"], ib, rs2, cap, TOL[prec])
+            seen.add(int(ctx.last_plan().split("splits=")[1].split()[0]))
+    finally:
+        ctx.set_plan(0, 0, 0)
+    assert {2, 4, 5, 14, 17, 34, 68} <= seen, seen
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_segment_rebuild(ctx, prec):
     """Rows with hundreds of neighbours per j-range overflow the per-split
     scratch segments; the merge must rebuild them in ascending order."""
