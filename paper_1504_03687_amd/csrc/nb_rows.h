@@ -269,6 +269,14 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTil
 #pragma unroll
     for (int r = 0; r < IR; ++r) row_init(R[r], a, row0 + r * kBlock + tid, row_end, d, near);
 
+    // a wave none of whose lanes holds a valid row (the tail of a cluster's
+    // last row tile) skips the pair loop; it still stages its share of every
+    // tile and meets every barrier
+    bool mine = false;
+#pragma unroll
+    for (int r = 0; r < IR; ++r) mine = mine || R[r].i >= 0;
+    const bool wave_busy = __ballot(mine) != 0;
+
     const int64_t ntiles = j1 > j0 ? (j1 - j0 + kTile - 1) / kTile : 0;
     JBody nxt;
     if (ntiles > 0) {
@@ -281,7 +289,7 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTil
         const int64_t tbase = j0 + t * kTile;
         if (t + 1 < ntiles) load_body(nxt, a, tbase + kTile + tid, j1);
         const JBody *buf = tile[cur];
-        for (int jj = 0; jj < kTile; jj += kFold) {
+        for (int jj = 0; jj < (wave_busy ? kTile : 0); jj += kFold) {
             for (int q = 0; q < kFold; q += 2) {
                 const int32_t jidx = (int32_t)(tbase + jj + q);
 #pragma unroll
