@@ -44,12 +44,27 @@ __device__ __forceinline__ double rsqrt_f64(double r2)
 template <bool MIXED>
 struct Sums;
 
+// FP64: the jerk is kept as two sums, sum m r^-3 u (jx..jz) and
+// sum m (r.u) r^-5 r (rx..rz), combined once by fold() as jx - 3 rx, so the
+// factor -3 is not multiplied in for every pair.  fold() must run before the
+// sums are read; it is idempotent.
 template <>
 struct Sums<false> {
     double ax, ay, az, jx, jy, jz;
     double va, vj;   // unused in FP64 (kept for a common slot layout)
-    __device__ __forceinline__ void zero() { ax = ay = az = jx = jy = jz = va = vj = 0.0; }
-    __device__ __forceinline__ void fold() {}
+    double rx, ry, rz;
+    __device__ __forceinline__ void zero()
+    {
+        ax = ay = az = jx = jy = jz = va = vj = 0.0;
+        rx = ry = rz = 0.0;
+    }
+    __device__ __forceinline__ void fold()
+    {
+        jx = __builtin_fma(-3.0, rx, jx);
+        jy = __builtin_fma(-3.0, ry, jy);
+        jz = __builtin_fma(-3.0, rz, jz);
+        rx = ry = rz = 0.0;
+    }
 };
 
 // va, vj: sums of the squared norms of the folded FP32 partials.  For terms of
@@ -103,13 +118,16 @@ __device__ __forceinline__ void accum_f64(Sums<false> &S, double dx, double dy, 
     const double y2 = y * y;
     const double mr3 = (mj * y) * y2;               // m / r^3
     const double s = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
-    const double q = (s * y2) * (-3.0 * mr3);       // -3 m (r.u) / r^5
+    const double q = (s * y2) * mr3;                // m (r.u) / r^5; -3 applied by fold()
     S.ax = __builtin_fma(mr3, dx, S.ax);
     S.ay = __builtin_fma(mr3, dy, S.ay);
     S.az = __builtin_fma(mr3, dz, S.az);
-    S.jx = __builtin_fma(q, dx, __builtin_fma(mr3, ux, S.jx));
-    S.jy = __builtin_fma(q, dy, __builtin_fma(mr3, uy, S.jy));
-    S.jz = __builtin_fma(q, dz, __builtin_fma(mr3, uz, S.jz));
+    S.jx = __builtin_fma(mr3, ux, S.jx);
+    S.jy = __builtin_fma(mr3, uy, S.jy);
+    S.jz = __builtin_fma(mr3, uz, S.jz);
+    S.rx = __builtin_fma(q, dx, S.rx);
+    S.ry = __builtin_fma(q, dy, S.ry);
+    S.rz = __builtin_fma(q, dz, S.rz);
 }
 
 // Mixed regular term: FP32 arithmetic on the FP32-rounded FP64 differences.

@@ -308,6 +308,7 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTil
     bool ovf = false, bad = false, nonfin = false;
 #pragma unroll
     for (int r = 0; r < IR; ++r) {
+        if constexpr (!MIXED) R[r].S.fold();
         const int64_t b = row0 + r * kBlock + tid;
         if (b < row_end) {
             bool o = false, bd = false, f = false;
@@ -530,6 +531,7 @@ __device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_
         }
         accum_f64(S, dx, dy, dz, r2, J.vx - vxi, J.vy - vyi, J.vz - vzi, J.m, excl);
     }
+    S.fold();
     out[0] = S.ax;
     out[1] = S.ay;
     out[2] = S.az;
@@ -594,6 +596,7 @@ __device__ __forceinline__ void redo_chunk_rows(const ForceArgs &a, int32_t q0, 
     }
 #pragma unroll
     for (int r = 0; r < kRedoRows; ++r) {
+        S[r].fold();
         out[r * 6 + 0] = S[r].ax;
         out[r * 6 + 1] = S[r].ay;
         out[r * 6 + 2] = S[r].az;
