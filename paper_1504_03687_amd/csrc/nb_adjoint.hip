@@ -123,8 +123,12 @@ __global__ __launch_bounds__(kBlock) void adj_rows_kernel(AdjointArgs a, AdjPlan
             hi = cand_bound_f64(rs2f);
         }
     }
-    // sum_j g_r = A C1 + B C2 + G,  sum_j g_u = B C1 + U
-    double C1 = 0, C2 = 0, Gx = 0, Gy = 0, Gz = 0, Ux = 0, Uy = 0, Uz = 0;
+    // With k5 = m R5 and t = k5 (B.r):
+    //   sum_j g_r = A C1 - 3 (B C2 + H),  sum_j g_u = B C1 - 3 U,
+    //   C1 = sum m R3,  C2 = sum k5 s,  U = sum t r,
+    //   H = sum [t u + k5 ((A.r + B.u) - 5 s (B.r) |r|^-2) r];
+    // the factor -3 is applied once per row.
+    double C1 = 0, C2 = 0, Hx = 0, Hy = 0, Hz = 0, Ux = 0, Uy = 0, Uz = 0;
 
     const int64_t ntiles = j1 > j0 ? (j1 - j0 + kTile - 1) / kTile : 0;
     JB nxt;
@@ -148,35 +152,35 @@ __global__ __launch_bounds__(kBlock) void adj_rows_kernel(AdjointArgs a, AdjPlan
             double y = rsqrt_f64(r2);
             y = excl ? 0.0 : y;
             const double y2 = y * y;
-            const double R3 = y * y2, R5 = R3 * y2, R7 = R5 * y2;
+            const double R3 = y * y2, R5 = R3 * y2;
             const double s = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
             const double Ar = __builtin_fma(Az, dz, __builtin_fma(Ay, dy, Ax * dx));
             const double Br = __builtin_fma(Bz, dz, __builtin_fma(By, dy, Bx * dx));
             const double Bu = __builtin_fma(Bz, uz, __builtin_fma(By, uy, Bx * ux));
             const double m = J.m;
-            const double mR5 = m * R5;
-            const double c3 = m * __builtin_fma(15.0 * (s * Br), R7, -3.0 * (R5 * (Ar + Bu)));
-            const double c2Br = -3.0 * mR5 * Br;
+            const double k5 = m * R5;
+            const double tb = k5 * Br;
+            const double c = k5 * __builtin_fma(-5.0 * (s * Br), y2, Ar + Bu);
             C1 = __builtin_fma(m, R3, C1);
-            C2 = __builtin_fma(-3.0 * mR5, s, C2);
-            Gx = __builtin_fma(c3, dx, __builtin_fma(c2Br, ux, Gx));
-            Gy = __builtin_fma(c3, dy, __builtin_fma(c2Br, uy, Gy));
-            Gz = __builtin_fma(c3, dz, __builtin_fma(c2Br, uz, Gz));
-            Ux = __builtin_fma(c2Br, dx, Ux);
-            Uy = __builtin_fma(c2Br, dy, Uy);
-            Uz = __builtin_fma(c2Br, dz, Uz);
+            C2 = __builtin_fma(k5, s, C2);
+            Hx = __builtin_fma(tb, ux, __builtin_fma(c, dx, Hx));
+            Hy = __builtin_fma(tb, uy, __builtin_fma(c, dy, Hy));
+            Hz = __builtin_fma(tb, uz, __builtin_fma(c, dz, Hz));
+            Ux = __builtin_fma(tb, dx, Ux);
+            Uy = __builtin_fma(tb, dy, Uy);
+            Uz = __builtin_fma(tb, dz, Uz);
         }
         if (t + 1 < ntiles) tile[cur ^ 1][tid] = nxt;
         __syncthreads();
     }
     if (b < a.n_i) {
         double *o = p.row_partial + (int64_t)split * 6 * a.n_i + b;
-        o[0] = __builtin_fma(Ax, C1, __builtin_fma(Bx, C2, Gx));
-        o[a.n_i] = __builtin_fma(Ay, C1, __builtin_fma(By, C2, Gy));
-        o[2 * (int64_t)a.n_i] = __builtin_fma(Az, C1, __builtin_fma(Bz, C2, Gz));
-        o[3 * (int64_t)a.n_i] = __builtin_fma(Bx, C1, Ux);
-        o[4 * (int64_t)a.n_i] = __builtin_fma(By, C1, Uy);
-        o[5 * (int64_t)a.n_i] = __builtin_fma(Bz, C1, Uz);
+        o[0] = __builtin_fma(Ax, C1, -3.0 * __builtin_fma(Bx, C2, Hx));
+        o[a.n_i] = __builtin_fma(Ay, C1, -3.0 * __builtin_fma(By, C2, Hy));
+        o[2 * (int64_t)a.n_i] = __builtin_fma(Az, C1, -3.0 * __builtin_fma(Bz, C2, Hz));
+        o[3 * (int64_t)a.n_i] = __builtin_fma(Bx, C1, -3.0 * Ux);
+        o[4 * (int64_t)a.n_i] = __builtin_fma(By, C1, -3.0 * Uy);
+        o[5 * (int64_t)a.n_i] = __builtin_fma(Bz, C1, -3.0 * Uz);
     }
 }
 
@@ -246,7 +250,15 @@ __global__ __launch_bounds__(kBlock) void adj_bodies_kernel(AdjointArgs a, AdjPl
         mj = a.m[j];
     }
     const int32_t jidx = live ? (int32_t)j : -2;
-    double Gx = 0, Gy = 0, Gz = 0, Ux = 0, Uy = 0, Uz = 0, M = 0;
+    // The body's own mass and the factor -3 are applied once per body:
+    //   dL/dx_j = m_j (GA - 3 GB) - D_x,  dL/dv_j = m_j (UA - 3 UB) - D_v,
+    //   dL/dm_j = MA - 3 MB,
+    // GA = sum R3 A, GB = sum [R5 s B + R5 (B.r) u + R5 ((A.r + B.u) - 5 s (B.r) |r|^-2) r],
+    // UA = sum R3 B, UB = sum R5 (B.r) r, MA = sum (A.r + B.u) R3, MB = sum s (B.r) R5,
+    // and D the row-pass sums of the rows whose body is j (in row order).
+    double GAx = 0, GAy = 0, GAz = 0, GBx = 0, GBy = 0, GBz = 0;
+    double UAx = 0, UAy = 0, UAz = 0, UBx = 0, UBy = 0, UBz = 0, MA = 0, MB = 0;
+    double Dx = 0, Dy = 0, Dz = 0, Dux = 0, Duy = 0, Duz = 0;
 
     const int64_t ntiles = b1 > b0 ? (b1 - b0 + kRowTile - 1) / kRowTile : 0;
     RB nxt;
@@ -270,36 +282,41 @@ __global__ __launch_bounds__(kBlock) void adj_bodies_kernel(AdjointArgs a, AdjPl
             double y = rsqrt_f64(r2);
             y = excl ? 0.0 : y;
             const double y2 = y * y;
-            const double R3 = y * y2, R5 = R3 * y2, R7 = R5 * y2;
+            const double R3 = y * y2, R5 = R3 * y2;
             const double s = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
             const double Ar = __builtin_fma(R.az, dz, __builtin_fma(R.ay, dy, R.ax * dx));
             const double Br = __builtin_fma(R.bz, dz, __builtin_fma(R.by, dy, R.bx * dx));
             const double Bu = __builtin_fma(R.bz, uz, __builtin_fma(R.by, uy, R.bx * ux));
             const double AB = Ar + Bu;
-            // dL/dm_j
-            M = __builtin_fma(AB, R3, __builtin_fma(-3.0 * (s * Br), R5, M));
-            const double c1 = mj * R3;
-            const double c2 = -3.0 * mj * R5;
-            const double c3 = mj * __builtin_fma(15.0 * (s * Br), R7, -3.0 * (R5 * AB));
-            const double c2Br = c2 * Br;
-            const double c2s = c2 * s;
-            Gx = __builtin_fma(c3, dx, __builtin_fma(c2Br, ux, __builtin_fma(c2s, R.bx, __builtin_fma(c1, R.ax, Gx))));
-            Gy = __builtin_fma(c3, dy, __builtin_fma(c2Br, uy, __builtin_fma(c2s, R.by, __builtin_fma(c1, R.ay, Gy))));
-            Gz = __builtin_fma(c3, dz, __builtin_fma(c2Br, uz, __builtin_fma(c2s, R.bz, __builtin_fma(c1, R.az, Gz))));
-            Ux = __builtin_fma(c2Br, dx, __builtin_fma(c1, R.bx, Ux));
-            Uy = __builtin_fma(c2Br, dy, __builtin_fma(c1, R.by, Uy));
-            Uz = __builtin_fma(c2Br, dz, __builtin_fma(c1, R.bz, Uz));
+            const double sBr = s * Br;
+            MA = __builtin_fma(AB, R3, MA);
+            MB = __builtin_fma(sBr, R5, MB);
+            const double R5s = R5 * s;
+            const double R5Br = R5 * Br;
+            const double cr = R5 * __builtin_fma(-5.0 * sBr, y2, AB);
+            GAx = __builtin_fma(R3, R.ax, GAx);
+            GAy = __builtin_fma(R3, R.ay, GAy);
+            GAz = __builtin_fma(R3, R.az, GAz);
+            GBx = __builtin_fma(R5s, R.bx, __builtin_fma(R5Br, ux, __builtin_fma(cr, dx, GBx)));
+            GBy = __builtin_fma(R5s, R.by, __builtin_fma(R5Br, uy, __builtin_fma(cr, dy, GBy)));
+            GBz = __builtin_fma(R5s, R.bz, __builtin_fma(R5Br, uz, __builtin_fma(cr, dz, GBz)));
+            UAx = __builtin_fma(R3, R.bx, UAx);
+            UAy = __builtin_fma(R3, R.by, UAy);
+            UAz = __builtin_fma(R3, R.bz, UAz);
+            UBx = __builtin_fma(R5Br, dx, UBx);
+            UBy = __builtin_fma(R5Br, dy, UBy);
+            UBz = __builtin_fma(R5Br, dz, UBz);
             // this body is the row's own body: subtract the row pass sum
             int32_t ri = R.i;
             if (ri == jidx) {
                 opaque(ri);
                 const double *rp = a.row_part + R.b;
-                Gx -= rp[0];
-                Gy -= rp[a.n_i];
-                Gz -= rp[2 * (int64_t)a.n_i];
-                Ux -= rp[3 * (int64_t)a.n_i];
-                Uy -= rp[4 * (int64_t)a.n_i];
-                Uz -= rp[5 * (int64_t)a.n_i];
+                Dx += rp[0];
+                Dy += rp[a.n_i];
+                Dz += rp[2 * (int64_t)a.n_i];
+                Dux += rp[3 * (int64_t)a.n_i];
+                Duy += rp[4 * (int64_t)a.n_i];
+                Duz += rp[5 * (int64_t)a.n_i];
             }
         }
         if (t + 1 < ntiles && tid < kRowTile) tile[cur ^ 1][tid] = nxt;
@@ -307,13 +324,13 @@ __global__ __launch_bounds__(kBlock) void adj_bodies_kernel(AdjointArgs a, AdjPl
     }
     if (live) {
         double *o = p.body_partial + (int64_t)split * 7 * a.n + j;
-        o[0] = Gx;
-        o[a.n] = Gy;
-        o[2 * a.n] = Gz;
-        o[3 * a.n] = Ux;
-        o[4 * a.n] = Uy;
-        o[5 * a.n] = Uz;
-        o[6 * a.n] = M;
+        o[0] = mj * __builtin_fma(-3.0, GBx, GAx) - Dx;
+        o[a.n] = mj * __builtin_fma(-3.0, GBy, GAy) - Dy;
+        o[2 * a.n] = mj * __builtin_fma(-3.0, GBz, GAz) - Dz;
+        o[3 * a.n] = mj * __builtin_fma(-3.0, UBx, UAx) - Dux;
+        o[4 * a.n] = mj * __builtin_fma(-3.0, UBy, UAy) - Duy;
+        o[5 * a.n] = mj * __builtin_fma(-3.0, UBz, UAz) - Duz;
+        o[6 * a.n] = __builtin_fma(-3.0, MB, MA);
     }
 }
 
