@@ -133,7 +133,7 @@ def radius_leg(nb, W, s, ctx, dev, x, v, a, jk, m, precs, L=10, cap=48, nnbopt=4
     the same block and cap."""
     import torch
     n = s["n"]
-    tl, t0l, bl = W.config3_level(s, L)
+    tl, t0l, bl = W.binary_cluster_level(s, L)
     xp, vp, _ = nb.predict(x, v, a, jk, dev(t0l), tl, ctx=ctx)
     bd = dev(bl)
     rs2_0 = dev(s["rs2"][bl])
@@ -275,9 +275,9 @@ def main():
 
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     t_gen = time.time()
-    s = W.config3(args.n)
+    s = W.binary_cluster_n1m(args.n)
     n = s["n"]
-    t, t0, blk = W.config3_level(s, 3)
+    t, t0, blk = W.binary_cluster_level(s, 3)
     log(f"workload generated in {time.time() - t_gen:.1f}s: n={n} full block={blk.size}")
     x, v, a, jk, m = dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(s["m"])
     t0d, ibd, rs2d = dev(t0), dev(blk), dev(s["rs2"][blk])
@@ -342,7 +342,7 @@ def main():
         tot_pairs = {p: 0.0 for p in precs}
         tot_time = {p: 0.0 for p in precs}
         for L in range(3, 21):
-            tl, t0l, bl = W.config3_level(s, L)
+            tl, t0l, bl = W.binary_cluster_level(s, L)
             if bl.size == 0:
                 continue
             w = W.level_weight(L)
@@ -398,7 +398,7 @@ def main():
     # (256 clusters, one graph launch), each timed over a few calls
     extras = {}
     if not args.no_levels:
-        s5 = W.config5()
+        s5 = W.adjoint_plummer_n65536()
         n5 = s5["n"]
         a5 = [dev(s5[k]) for k in ("x", "v", "m", "i_block", "rs2", "w_a", "w_j")]
         nb.regular_force_adjoint(*a5, ctx=ctx)
@@ -412,7 +412,7 @@ def main():
                              "ms": round(ms, 3),
                              "gpairs_per_s_per_pass": round(n5 * (n5 - 1) / ms * 1e-6, 2)}
         log(f"adjoint: {ms:.2f} ms")
-        s4 = W.config4()
+        s4 = W.cluster_ensemble_256()
         xp4, vp4, _ = nb.predict(dev(s4["x"]), dev(s4["v"]), dev(s4["a"]), dev(s4["jk"]),
                                  dev(s4["t0"]), s4["t"], ctx=ctx)
         b4 = (s4["j_off"], s4["i_off"], xp4, vp4, dev(s4["m"]), dev(s4["i_block"]),

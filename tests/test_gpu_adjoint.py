@@ -73,16 +73,16 @@ def test_adjoint_bad_index_and_empty(ctx):
     assert not any(host(t).any() for t in e)
 
 
-def test_config5_adjoint(ctx):
+def test_adjoint_n65536(ctx):
     """N = 65536 Plummer + Kroupa: the 1024-row subset against the oracle's
     gradient, and the all-active block against central differences (h = 1e-6)
     of local losses at sampled bodies."""
-    s = W.config5()
+    s = W.adjoint_plummer_n65536()
     x, v, m = s["x"], s["v"], s["m"]
-    say("config5 subset")
+    say("adjoint N=65536 subset")
     sub = np.random.default_rng(5).choice(s["n"], 1024, replace=False).astype(np.int32)
     _check_vs_oracle(ctx, x, v, m, sub, s["rs2"][sub], s["w_a"][:, sub], s["w_j"][:, sub])
-    say("config5 full block vs finite differences")
+    say("adjoint N=65536 full block vs finite differences")
     ib, rs2, wa, wj = s["i_block"], s["rs2"], s["w_a"], s["w_j"]
     gx, gv, gm = (host(t) for t in nb.regular_force_adjoint(
         dev(x), dev(v), dev(m), dev(ib), dev(rs2), dev(wa), dev(wj), ctx=ctx))

@@ -109,10 +109,12 @@ def test_batched_graph_replay_sees_new_data(ctx):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("splits", [1, 3])
+@pytest.mark.parametrize("splits", [1, 3, 7, 16])
 def test_batched_equals_single_launches(ctx, prec, splits):
     """Each cluster of the batch gives bit-identical rows to a single-block
-    launch of the same plan on that cluster alone."""
+    launch of the same plan on that cluster alone.  At 7 and 16 requested
+    splits the clusters get 1 to 12 splits, so the batched merge runs 16-lane
+    row groups on clusters whose own launch merges with 4-lane groups."""
     say(f"batched vs single {prec} splits={splits}")
     E = _ensemble(seed=11)
     ctx.set_plan(1, 1, splits)
@@ -138,12 +140,12 @@ def test_batched_equals_single_launches(ctx, prec, splits):
         ctx.set_plan(0, 0, 0)
 
 
-def test_config4_ensemble(ctx):
+def test_cluster_ensemble_256(ctx):
     """256 Plummer + Kroupa clusters, N log-uniform in [1024, 32768], active
     fractions U[0.01, 1]: one persistent launch, sampled rows of every cluster
     against the oracle."""
-    s = W.config4()
-    say(f"config4: {s['n']} bodies, {s['i_block'].size} rows")
+    s = W.cluster_ensemble_256()
+    say(f"ensemble: {s['n']} bodies, {s['i_block'].size} rows")
     xp, vp, _ = nb.predict(dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(s["t0"]),
                            s["t"], ctx=ctx)
     ox, ov = oracle.predict(s["t"], s["x"], s["v"], s["a"], s["jk"], s["t0"])

@@ -53,10 +53,10 @@ def test_predict_bitwise(ctx, n):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_config1_all_active(ctx, prec):
+def test_plummer_n1024_all_active(ctx, prec):
     """N = 1024 equal-mass Plummer, every body active, nb_cap 256."""
-    say(f"config1 {prec}")
-    s = W.config1()
+    say(f"plummer N=1024 {prec}")
+    s = W.plummer_equal_n1024()
     xp, vp, _ = _predict_dev(ctx, s)
     ox, ov = oracle.predict(s["t"], s["x"], s["v"], s["a"], s["jk"], s["t0"])
     assert np.array_equal(host(xp), ox) and np.array_equal(host(vp), ov)
@@ -217,16 +217,16 @@ def test_power_of_two_scaling_fp64(ctx):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_config2_blocks(ctx, prec):
+def test_plummer_kroupa_n131072_blocks(ctx, prec):
     """N = 131072 Plummer + Kroupa: random blocks of 1, 32, 1024, 16384 rows
     in full and the all-active block on 512 sampled rows."""
-    s = W.config2()
+    s = W.plummer_kroupa_n131072()
     xp, vp, _ = _predict_dev(ctx, s)
     ox, ov = oracle.predict(s["t"], s["x"], s["v"], s["a"], s["jk"], s["t0"])
     assert np.array_equal(host(xp), ox)
     m = dev(s["m"])
     for size, blk in s["blocks"].items():
-        say(f"config2 {prec} n_i={size}")
+        say(f"plummer-kroupa N=131072 {prec} n_i={size}")
         rs2 = s["rs2"][blk]
         res = nb.regular_force(xp, vp, m, dev(blk), dev(rs2), s["nb_cap"], prec, ctx=ctx)
         rows = None if size <= 16384 else np.random.default_rng(size).choice(size, 512,
@@ -235,7 +235,7 @@ def test_config2_blocks(ctx, prec):
         say(f"  plan {ctx.last_plan()}  err acc {ea:.2e} jerk {ej:.2e}")
 
 
-def _config3_sample_rows(s, blk, k=384):
+def _million_body_sample_rows(s, blk, k=384):
     """Rows of block blk to check: the most central bodies, binary components
     and a random remainder."""
     r = np.sqrt((s["x"] ** 2).sum(0))[blk]
@@ -247,17 +247,17 @@ def _config3_sample_rows(s, blk, k=384):
 
 
 @pytest.mark.parametrize("level", [3, 12])
-def test_config3_million_body(ctx, level):
+def test_million_body_cluster(ctx, level):
     """N = 2^20 Plummer + Kroupa with 5% binaries, both precisions, at the full
     block (level 3) and a deep block level; sampled rows vs the oracle."""
-    s = W.config3()
-    t, t0, blk = W.config3_level(s, level)
-    say(f"config3 level {level}: n_i={blk.size}")
+    s = W.binary_cluster_n1m()
+    t, t0, blk = W.binary_cluster_level(s, level)
+    say(f"N=2^20 cluster level {level}: n_i={blk.size}")
     xp, vp, _ = nb.predict(dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(t0), t,
                            ctx=ctx)
     ox, ov = oracle.predict(t, s["x"], s["v"], s["a"], s["jk"], t0)
     assert np.array_equal(host(xp), ox) and np.array_equal(host(vp), ov)
-    rows = _config3_sample_rows(s, blk)
+    rows = _million_body_sample_rows(s, blk)
     m = dev(s["m"])
     rs2 = s["rs2"][blk]
     keep = {}

@@ -97,11 +97,11 @@ def test_fit_round_limit_and_no_overflow(ctx):
     _compare_fit(got, ref, big, TOL_FP64)
 
 
-def test_fit_config2_block(ctx):
+def test_fit_n131072_block(ctx):
     """N = 131072 Plummer + Kroupa, a random block of 4096 rows with radii
     from the 64th neighbour and a list cap of 56: most rows overflow."""
-    say("fit config 2")
-    s = W.config2()
+    say("fit N=131072")
+    s = W.plummer_kroupa_n131072()
     rng = np.random.default_rng(860)
     blk = np.sort(rng.choice(s["n"], 4096, replace=False)).astype(np.int32)
     rs2 = s["rs2"][blk].copy()
@@ -123,13 +123,13 @@ def test_fit_config2_block(ctx):
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_fit_bench_configuration_sampled(ctx, prec):
-    """The fit as the benchmark runs it: N = 2^20 (config 3), the level-10
+    """The fit as the benchmark runs it: the N = 2^20 binary cluster, the level-10
     block (51374 rows), radii from the 64th neighbour, nb_cap 48, NNBOPT 40.
     Rows are independent in the fit, so the oracle's fit of 256 sampled rows
     alone must give those rows' radii, counts and lists bit for bit."""
     say(f"fit at the benchmark configuration {prec}")
-    s = W.config3()
-    t, t0, blk = W.config3_level(s, 10)
+    s = W.binary_cluster_n1m()
+    t, t0, blk = W.binary_cluster_level(s, 10)
     xp, vp, _ = nb.predict(dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(t0), t,
                            ctx=ctx)
     ox, ov = oracle.predict(t, s["x"], s["v"], s["a"], s["jk"], t0)

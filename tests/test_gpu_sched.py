@@ -176,10 +176,10 @@ def test_prefix_is_the_force_block(ctx):
 
 
 def test_bench_configuration_levels(ctx):
-    """The scheduler as the benchmark runs it: config 3's own step levels
+    """The scheduler as the benchmark runs it: the N = 2^20 binary cluster's own step levels
     (2^20 bodies, levels 3..20, k_max 20): the build is the oracle's list bit
     for bit, and each level's update keeps every level block's members."""
-    s = W.config3()
+    s = W.binary_cluster_n1m()
     lev = s["levels"].astype(np.int32)
     k_max = 20
     g_lev = dev(lev)

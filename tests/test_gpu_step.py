@@ -22,7 +22,7 @@ def ctx():
 
 def test_irregular_force_and_full_force(ctx):
     say("irregular force")
-    s = W.config2()
+    s = W.plummer_kroupa_n131072()
     xp, vp, m = dev(s["x"]), dev(s["v"]), dev(s["m"])
     blk = s["blocks"][16384]
     cap = 128
@@ -47,7 +47,7 @@ def test_irregular_force_and_full_force(ctx):
 def test_irregular_packed_and_plane_gathers_agree(ctx):
     """Large blocks gather neighbours from a packed copy of the bodies, small
     ones from the SoA planes: the same rows give bitwise-equal results."""
-    s = W.config2()
+    s = W.plummer_kroupa_n131072()
     xp, vp, m = dev(s["x"]), dev(s["v"]), dev(s["m"])
     blk = s["blocks"][16384]
     cap = 128
@@ -223,12 +223,12 @@ def test_hierarchical_block_steps_match_oracle(ctx):
 
 def test_step_kernels_bench_configuration(ctx):
     """The rest of the block step as the benchmark runs it, at the 2^20 full
-    block of config 3: the irregular force over the lists of the full-block
+    block of the N = 2^20 binary cluster: the irregular force over the lists of the full-block
     regular pass (packed gathers) on 256 sampled rows, the corrector on all
     2^20 entries bit for bit, and the potential at 256 sampled bodies."""
     say("block-step kernels at the benchmark configuration")
-    s = W.config3()
-    t, t0, blk = W.config3_level(s, 3)
+    s = W.binary_cluster_n1m()
+    t, t0, blk = W.binary_cluster_level(s, 3)
     n, cap = s["n"], s["nb_cap"]
     xp, vp, _ = nb.predict(dev(s["x"]), dev(s["v"]), dev(s["a"]), dev(s["jk"]), dev(t0), t,
                            ctx=ctx)

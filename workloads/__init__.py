@@ -28,13 +28,14 @@ SEED_BASE = 1504036870
 PLUMMER_B = 3.0 * math.pi / 16.0
 
 
-def rng_for(config: int, *spawn) -> np.random.Generator:
-    """Generator for workload ``config`` (1..5); ``spawn`` selects a child stream."""
+def rng_for(k: int, *spawn) -> np.random.Generator:
+    """Generator for workload number ``k`` (1..5: the five workload builders
+    below, in order); ``spawn`` selects a child stream."""
     if spawn:
-        ss = np.random.SeedSequence(SEED_BASE + config)
+        ss = np.random.SeedSequence(SEED_BASE + k)
         child = ss.spawn(spawn[0] + 1)[spawn[0]]
         return np.random.Generator(np.random.PCG64(child))
-    return np.random.Generator(np.random.PCG64(SEED_BASE + config))
+    return np.random.Generator(np.random.PCG64(SEED_BASE + k))
 
 
 # --------------------------------------------------------------------------- #
@@ -317,7 +318,7 @@ def uniform_step_state(rng, n, imf, dt_k=8, k_nn=64):
 
 
 @functools.lru_cache(maxsize=4)
-def config1():
+def plummer_equal_n1024():
     """N = 1024 equal-mass Plummer, all active, nb_cap 256, FP64."""
     s = uniform_step_state(rng_for(1), 1024, "equal")
     s["i_block"] = np.arange(1024, dtype=np.int32)
@@ -326,7 +327,7 @@ def config1():
 
 
 @functools.lru_cache(maxsize=4)
-def config2(n: int = 131072):
+def plummer_kroupa_n131072(n: int = 131072):
     """N = 131072 Plummer + Kroupa; random blocks of 1, 32, 1024, 16384, N."""
     rng = rng_for(2)
     s = uniform_step_state(rng, n, "kroupa")
@@ -337,7 +338,7 @@ def config2(n: int = 131072):
 
 
 @functools.lru_cache(maxsize=2)
-def config3(n: int = 1 << 20):
+def binary_cluster_n1m(n: int = 1 << 20):
     """N = 2^20 Plummer + Kroupa with n/40 primordial binaries (5% of bodies in
     binaries); Hermite step levels 3..20; nb_cap 1024."""
     rng = rng_for(3)
@@ -356,15 +357,15 @@ def config3(n: int = 1 << 20):
     return s
 
 
-def config3_level(s: dict, L: int):
-    """(t, t0, i_block) for block level L of a config-3 state; L = 3 is the full
+def binary_cluster_level(s: dict, L: int):
+    """(t, t0, i_block) for block level L of a binary_cluster_n1m state; L = 3 is the full
     block only if every body sits at level >= 3, which the clamp guarantees."""
     t = level_time(L)
     return t, level_t0(s["levels"], t), level_block(s["levels"], L)
 
 
 @functools.lru_cache(maxsize=2)
-def config4(n_clusters: int = 256, n_lo: int = 1024, n_hi: int = 32768):
+def cluster_ensemble_256(n_clusters: int = 256, n_lo: int = 1024, n_hi: int = 32768):
     """Ensemble of independent Plummer + Kroupa clusters, N log-uniform in
     [n_lo, n_hi], active fraction U[0.01, 1]; concatenated SoA with offsets."""
     rng = rng_for(4)
@@ -397,7 +398,7 @@ def config4(n_clusters: int = 256, n_lo: int = 1024, n_hi: int = 32768):
 
 
 @functools.lru_cache(maxsize=2)
-def config5(n: int = 65536):
+def adjoint_plummer_n65536(n: int = 65536):
     """N = 65536 Plummer + Kroupa, all active; random upstream weights."""
     rng = rng_for(5)
     s = uniform_step_state(rng, n, "kroupa")
