@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -71,6 +72,31 @@ def measured_traffic(prec: str):
     if d.get("kernel_src_sha1") != kernel_src_hash():
         return None
     return d.get(prec, {}).get("hbm_bytes_per_launch")
+
+
+def steady_ms(call, warm_ms=30.0, time_ms=50.0, min_reps=3):
+    """Mean wall time of one call in steady state.  The calls first run back
+    to back, untimed, for at least warm_ms (the GPU clock ramps up under
+    load: a few calls after an idle gap read up to 20% slow on the small
+    step levels); then at least min_reps calls and time_ms are timed."""
+    import torch
+    call()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    k = 0
+    while True:
+        call()
+        k += 1
+        torch.cuda.synchronize()
+        if (time.perf_counter() - t) * 1e3 >= warm_ms:
+            break
+    est = (time.perf_counter() - t) * 1e3 / k
+    reps = max(min_reps, int(math.ceil(time_ms / max(est, 1e-3))))
+    c1 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - c1) * 1e3 / reps
 
 
 def sched_leg(nb, W, s, ctx, dev, reps=20):
@@ -349,16 +375,10 @@ def main():
             bd, rd, t0ld = dev(bl), dev(s["rs2"][bl]), dev(t0l)
             ent = {"n_i": int(bl.size), "weight": w}
             for prec in precs:
-                nb.predict(x, v, a, jk, t0ld, tl, out=(xp, vp), ctx=ctx)
-                nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
-                torch.cuda.synchronize()
-                reps = 3
-                c1 = time.perf_counter()
-                for _ in range(reps):
+                def level_call():
                     nb.predict(x, v, a, jk, t0ld, tl, out=(xp, vp), ctx=ctx)
                     nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
-                torch.cuda.synchronize()
-                ms = (time.perf_counter() - c1) * 1e3 / reps
+                ms = steady_ms(level_call)
                 p = float(bl.size) * (n - 1)
                 ent[prec] = {"ms": round(ms, 4), "gpairs_per_s": round(p / ms * 1e-6, 2)}
                 tot_pairs[prec] += w * p
@@ -378,14 +398,8 @@ def main():
             bd, rd = dev(sb), dev(s["rs2"][sb])
             ent = {}
             for prec in precs:
-                nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
-                torch.cuda.synchronize()
-                reps = 20
-                c1 = time.perf_counter()
-                for _ in range(reps):
-                    nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
-                torch.cuda.synchronize()
-                us = (time.perf_counter() - c1) * 1e6 / reps
+                us = 1e3 * steady_ms(
+                    lambda: nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx))
                 ent[prec] = {"us": round(us, 1),
                              "gpairs_per_s": round(size * (n - 1) / us * 1e-3, 2),
                              "jset_GB_per_s": round(56.0 * n / us * 1e-3, 1),
@@ -395,19 +409,13 @@ def main():
                 f"{pp}={ent[pp]['us']} us" for pp in precs))
 
     # adjoint (N = 65536 all active, FP64) and the batched ensemble
-    # (256 clusters, one graph launch), each timed over a few calls
+    # (256 clusters, one graph launch), each timed in steady state
     extras = {}
     if not args.no_levels:
         s5 = W.adjoint_plummer_n65536()
         n5 = s5["n"]
         a5 = [dev(s5[k]) for k in ("x", "v", "m", "i_block", "rs2", "w_a", "w_j")]
-        nb.regular_force_adjoint(*a5, ctx=ctx)
-        torch.cuda.synchronize()
-        c1 = time.perf_counter()
-        for _ in range(3):
-            nb.regular_force_adjoint(*a5, ctx=ctx)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - c1) * 1e3 / 3
+        ms = steady_ms(lambda: nb.regular_force_adjoint(*a5, ctx=ctx))
         extras["adjoint"] = {"workload": f"N={n5} Plummer+Kroupa, all active, FP64",
                              "ms": round(ms, 3),
                              "gpairs_per_s_per_pass": round(n5 * (n5 - 1) / ms * 1e-6, 2)}
@@ -422,12 +430,8 @@ def main():
         pairs4 = float((sizes * rows).sum())
         for prec in precs:
             o4 = nb.regular_force_batched(*b4, s4["nb_cap"], prec, ctx=ctx)
-            torch.cuda.synchronize()
-            c1 = time.perf_counter()
-            for _ in range(5):
-                nb.regular_force_batched(*b4, s4["nb_cap"], prec, out=o4, ctx=ctx)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - c1) * 1e3 / 5
+            ms = steady_ms(
+                lambda: nb.regular_force_batched(*b4, s4["nb_cap"], prec, out=o4, ctx=ctx))
             extras[f"batched_{prec}"] = {
                 "workload": "256 clusters, N log-uniform [1024, 32768], active 1-100%",
                 "ms": round(ms, 3), "gpairs_per_s": round(pairs4 / ms * 1e-6, 2),
