@@ -123,6 +123,36 @@ def test_merge_group_widths(ctx, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bad_rows_in_merge_groups(ctx, prec):
+    """Rows with out-of-range body indices next to valid rows, merged by 4-,
+    16- and 64-lane groups: the bad rows get zero acc/jerk, count 0 and the
+    status bit; the valid rows match the oracle."""
+    n = 17308
+    s = W.small_state(43, n, k_nn=32)
+    rng = np.random.default_rng(43)
+    ib = rng.integers(0, n, 300).astype(np.int32)
+    bad = np.array([0, 1, 17, 64, 65, 299])
+    ib[bad[::2]] = -1
+    ib[bad[1::2]] = n + 3
+    rs2 = s["rs2"][np.clip(ib, 0, n - 1)]
+    good = np.setdiff1d(np.arange(ib.size), bad)
+    try:
+        for req in (3, 12, 40):
+            ctx.set_plan(1, 1, req)
+            say(f"bad rows {prec} splits requested {req}")
+            st = torch.zeros(1, dtype=torch.int32, device="cuda")
+            res = nb.regular_force(dev(s["x"]), dev(s["v"]), dev(s["m"]), dev(ib), dev(rs2), 32,
+                                   prec, status=st, ctx=ctx)
+            torch.cuda.synchronize()
+            assert int(st.item()) & nb.STATUS_BAD_INDEX
+            acc, jerk, cnt = host(res[0]), host(res[1]), host(res[2])
+            assert not acc[:, bad].any() and not jerk[:, bad].any() and not cnt[bad].any()
+            compare_force(res, s["x"], s["v"], s["m"], ib, rs2, 32, TOL[prec], rows=good)
+    finally:
+        ctx.set_plan(0, 0, 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_segment_rebuild(ctx, prec):
     """Rows with hundreds of neighbours per j-range overflow the per-split
     scratch segments; the merge must rebuild them in ascending order."""
