@@ -57,15 +57,24 @@ int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, i
     return std::max<int64_t>(1, std::min(s, max_splits(n, mapping)));
 }
 
+// Largest block that takes the wave mapping in the automatic plan.  Above it
+// the row-per-lane kernel is faster even with most lanes of its single row
+// tile idle: at N = 2^20 the crossover measured between 64 and 72 rows for
+// mixed (72 rows: 255 vs 291 us) and between 104 and 112 rows for FP64
+// (112 rows: 288 vs 292 us); at 192 rows the wave mapping took 648 / 478 us
+// against 285 / 370 us.
+constexpr int32_t kWaveMaxRowsMixed = 64;
+constexpr int32_t kWaveMaxRowsF64 = 104;
+
 // Automatic plan for a block of n_i rows against n bodies: the autotuned
 // entry for the size buckets if there is one, else the wave mapping for
-// n_i < 256 and one row per lane above.
+// small blocks and one row per lane above.
 Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed)
 {
     auto it = ctx->tuned.find(std::make_tuple((int)mixed, bucket_log2(n), bucket_log2(n_i)));
     if (it != ctx->tuned.end()) return it->second;
     Plan p{};
-    if (n_i < 256) {
+    if (n_i <= (mixed ? kWaveMaxRowsMixed : kWaveMaxRowsF64)) {
         p.mapping = 2;
         p.rows_per_lane = n_i >= 4 ? 4 : (n_i >= 2 ? 2 : 1);
     } else {
