@@ -53,18 +53,24 @@ int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, i
         units = (n_i + (int64_t)rows * nb::kBlock - 1) / ((int64_t)rows * nb::kBlock);
         target = cus * 64;                                      // work-groups
     }
-    const int64_t s = (target + std::max<int64_t>(units, 1) - 1) / std::max<int64_t>(units, 1);
+    // mapping 2 rounds down: with only ~2 work-groups per CU, one wave group
+    // past the target puts a third work-group on some CU and stretches the
+    // whole launch by half (72 rows at N = 2^20: 2052 waves took 257 us,
+    // against 152 us for 64 rows in 2048 waves).  finish_plan can only lower
+    // the count further.  Mapping 1 rounds up: at ~64 work-groups per CU one
+    // extra costs little.
+    const int64_t u = std::max<int64_t>(units, 1);
+    const int64_t s = mapping == 2 ? std::max<int64_t>(1, target / u) : (target + u - 1) / u;
     return std::max<int64_t>(1, std::min(s, max_splits(n, mapping)));
 }
 
 // Largest block that takes the wave mapping in the automatic plan.  Above it
 // the row-per-lane kernel is faster even with most lanes of its single row
-// tile idle: at N = 2^20 the crossover measured between 64 and 72 rows for
-// mixed (72 rows: 255 vs 291 us) and between 104 and 112 rows for FP64
-// (112 rows: 288 vs 292 us); at 192 rows the wave mapping took 648 / 478 us
-// against 285 / 370 us.
-constexpr int32_t kWaveMaxRowsMixed = 64;
-constexpr int32_t kWaveMaxRowsF64 = 104;
+// tile idle.  Measured at N = 2^20 (steady state): mixed 128 rows 253 us
+// (wave) vs 259 us, 160 rows 326 vs 277 us; FP64 160 rows 290 vs 342 us,
+// 192 rows 340 vs 344 us, 255 rows 430 vs 375 us.
+constexpr int32_t kWaveMaxRowsMixed = 128;
+constexpr int32_t kWaveMaxRowsF64 = 192;
 
 // Automatic plan for a block of n_i rows against n bodies: the autotuned
 // entry for the size buckets if there is one, else the wave mapping for
