@@ -22,14 +22,16 @@ int64_t bucket_log2(int64_t v)
 }
 
 // Largest useful split count: splits of about 4 waves' worth of bodies in the
-// wave mapping, 3 tiles in the row-per-lane mapping.  With a row's split
-// partials contiguous the merge stays cheap at high split counts, and at
-// N = 2^20 the 1272-row block ran 14% faster (mixed) with 3-tile splits (1366
-// of them) than with the earlier 8-tile floor (512); shorter splits were not
-// tried.
+// wave mapping, 2 tiles in the row-per-lane mapping.  With a row's split
+// partials contiguous the merge stays cheap at high split counts.  At
+// N = 2^20: the 1272-row block ran 14% faster (mixed) with 3-tile splits
+// (1366) than with the earlier 8-tile floor (512), and 2-tile splits (2048)
+// tie with 3-tile ones there; a single row tile (255 rows) took 308 us with
+// 2048 splits, 339 us with 1366 and 318 us with 1024 (mixed; FP64 353 / 387 /
+// 362 us): 2048 work-groups spread evenly over 256 CUs.
 int64_t max_splits(int64_t n, int mapping)
 {
-    const int64_t unit = mapping == 2 ? 4 * nb::kWave : 3 * nb::kTile;
+    const int64_t unit = mapping == 2 ? 4 * nb::kWave : 2 * nb::kTile;
     return std::max<int64_t>(1, (n + unit - 1) / unit);
 }
 
