@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 # (acc + jerk, FMA counted as 2): r = xj - xi (3), u = vj - vi (3), r.r (5),
 # r.u (5), 1/sqrt (1), r^-2 (1), m r^-3 (2), 3 (r.u) r^-2 (2), acc += m r^-3 r
 # (6), jerk += m r^-3 (u - alpha r) (12).
-FLOPS_PER_PAIR = 39
+FLOPS_PER_PAIR = 40
 # MI355X published vector peaks (TFLOP/s): FP32 157.3 (with packed FP32
 # instructions), FP64 78.6.  256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz =
 # 78.6 TFLOP/s is also the ceiling of unpacked FP32.

@@ -133,6 +133,27 @@ def _dev(t, name, dtype, shape=None):
     return t
 
 
+def _force_outputs(out, n_i: int, nb_cap: int, device):
+    """The five output tensors of a regular-force call: new ones, or the
+    caller's (acc, jerk, nb_count, nb_list, overflow), each checked for
+    device, dtype, shape and contiguity before any pointer reaches the
+    library (an undersized list would be written past its end)."""
+    if nb_cap < 0:
+        raise ValueError("nb_cap must be >= 0")
+    shapes = (("acc", torch.float64, (3, n_i)), ("jerk", torch.float64, (3, n_i)),
+              ("nb_count", torch.int32, (n_i,)), ("nb_list", torch.int32, (n_i, nb_cap)),
+              ("overflow", torch.int32, (1,)))
+    if out is None:
+        return tuple(torch.empty(shape, dtype=dt, device=device) for _, dt, shape in shapes)
+    if not isinstance(out, (tuple, list)) or len(out) != 5:
+        raise ValueError("out must be (acc, jerk, nb_count, nb_list, overflow)")
+    for t, (name, dt, shape) in zip(out, shapes):
+        _dev(t, f"out {name}", dt, shape)
+        if t.device != device:
+            raise ValueError(f"out {name} is on {t.device}, the inputs on {device}")
+    return tuple(out)
+
+
 class Context:
     """One libnbreg context on one device.  Calls launch on torch's current
     stream of that device at the time of the call."""
@@ -264,14 +285,7 @@ def regular_force(xp, vp, m, i_block, rs2, nb_cap: int, precision="fp64", status
     if nb_cap < 0:
         raise ValueError("nb_cap must be >= 0")
     dev = xp.device
-    if out is None:
-        acc = torch.empty((3, n_i), dtype=torch.float64, device=dev)
-        jerk = torch.empty((3, n_i), dtype=torch.float64, device=dev)
-        cnt = torch.empty(n_i, dtype=torch.int32, device=dev)
-        lst = torch.empty((n_i, nb_cap), dtype=torch.int32, device=dev)
-        ovf = torch.empty(1, dtype=torch.int32, device=dev)
-    else:
-        acc, jerk, cnt, lst, ovf = out
+    acc, jerk, cnt, lst, ovf = _force_outputs(out, n_i, nb_cap, dev)
     if status is not None:
         _dev(status, "status", torch.int32, (1,))
     ctx = ctx or context(dev.index)
@@ -328,14 +342,7 @@ def regular_force_batched(j_off, i_off, xp, vp, m, i_block, rs2, nb_cap: int,
     _dev(i_block, "i_block", torch.int32, (n_rows,))
     _dev(rs2, "rs2", torch.float64, (n_rows,))
     dev = xp.device
-    if out is None:
-        acc = torch.empty((3, n_rows), dtype=torch.float64, device=dev)
-        jerk = torch.empty((3, n_rows), dtype=torch.float64, device=dev)
-        cnt = torch.empty(n_rows, dtype=torch.int32, device=dev)
-        lst = torch.empty((n_rows, nb_cap), dtype=torch.int32, device=dev)
-        ovf = torch.empty(1, dtype=torch.int32, device=dev)
-    else:
-        acc, jerk, cnt, lst, ovf = out
+    acc, jerk, cnt, lst, ovf = _force_outputs(out, n_rows, nb_cap, dev)
     if status is not None:
         _dev(status, "status", torch.int32, (1,))
     ctx = ctx or context(dev.index)

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <vector>
 
 #include "nbreg.h"
@@ -114,7 +115,9 @@ extern "C" int nb_autotune(nb_ctx *ctx, int64_t n, const char *cache_path, int f
     // rows: a fixed stride permutation of the bodies
     std::vector<int32_t> ib(max_ni);
     std::vector<double> rrs2(max_ni);
-    const int64_t stride = 40503;   // odd, so i -> i*stride mod n is a bijection for even n
+    // i -> i * stride mod n is a bijection when gcd(stride, n) = 1
+    int64_t stride = 40503;
+    while (std::gcd(stride, n) != 1) stride += 2;
     for (int32_t k = 0; k < max_ni; ++k) {
         ib[k] = (int32_t)(((int64_t)k * stride) % n);
         rrs2[k] = hrs2[ib[k]];

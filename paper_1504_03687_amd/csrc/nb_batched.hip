@@ -147,8 +147,11 @@ struct BatchedCache {
 
 static uint64_t g_use_clock = 0;
 
-static void release_one(BatchedCache *c)
+static void release_one(nb_ctx *ctx, BatchedCache *c)
 {
+    // the refinement counter of the last call may live in this cache
+    if (ctx && c->args.f.redo_count && ctx->last_redo_counter == c->args.f.redo_count)
+        ctx->last_redo_counter = nullptr;
     if (c->exec) (void)hipGraphExecDestroy(c->exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->dmem) (void)hipFree(c->dmem);
@@ -157,7 +160,7 @@ static void release_one(BatchedCache *c)
 
 void batched_release(nb_ctx *ctx)
 {
-    for (auto *c : ctx->batched) release_one(c);
+    for (auto *c : ctx->batched) release_one(ctx, c);
     ctx->batched.clear();
 }
 
@@ -288,7 +291,9 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     A.f = f;
     nb::bind_slot_scratch(A.f, slots, dslots);
     A.f.redo_k = c->redo_k;
-    if (c->redo_k > 0.0) nb::bind_redo_scratch(A.f, dredo, groups, max_len);
+    // the refinement counter sits in the queue's 256-byte block, away from the
+    // work counter's word
+    if (c->redo_k > 0.0) nb::bind_redo_scratch(A.f, dredo, queue + 32, groups, max_len);
     A.f.splits = 0;          // per-cluster
     A.f.split_len = 0;
     A.clusters = dcl;
@@ -380,7 +385,7 @@ extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const i
                                         });
             hipError_t e = hipStreamSynchronize(ctx->stream);
             if (e != hipSuccess) return hip_fail(ctx, e);
-            release_one(*old);
+            release_one(ctx, *old);
             ctx->batched.erase(old);
         }
         auto *c = new BatchedCache();
@@ -409,7 +414,7 @@ extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const i
         f.status = status;
         int rc = build_cache(ctx, c, f, mixed);
         if (rc != NB_OK) {
-            release_one(c);
+            release_one(ctx, c);
             return rc;
         }
         ctx->batched.push_back(c);

@@ -118,8 +118,9 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
                 const float r2f = __builtin_fmaf(fz, fz, __builtin_fmaf(fy, fy, fx * fx));
                 const bool cand = r2f < candf[g];
                 if (__ballot(cand)) {   // neighbours, self, near pairs (FP64 terms)
+                    // lanes past j1 hold padding (mass 0): never a neighbour
                     const bool self = cand && jidx == ri[g];
-                    const bool nbr = cand && (r2f < rs2f[g]) && !self;
+                    const bool nbr = cand && (r2f < rs2f[g]) && !self && j < j1;
                     const uint64_t nm = __ballot(nbr);
                     if (nbr) {
                         const int p = cnt[g] + lanes_below(nm);
@@ -138,7 +139,8 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
                 bool excl = false;
                 if (__ballot(cand)) {
                     const bool self = cand && jidx == ri[g];
-                    const bool nbr = cand && (canon_r2f(dx, dy, dz) < rs2f[g]) && !self;
+                    const bool nbr =
+                        cand && (canon_r2f(dx, dy, dz) < rs2f[g]) && !self && j < j1;
                     const uint64_t nm = __ballot(nbr);
                     if (nbr) {
                         const int p = cnt[g] + lanes_below(nm);
@@ -324,35 +326,37 @@ static int32_t redo_chunks_for(int64_t max_len)
     return (int32_t)(c > 0 ? c : 1);
 }
 
-static int32_t redo_rcap_for(int32_t n_i, int32_t chunks)
+static int32_t redo_rcap_for(int32_t n_i, int32_t chunks, int32_t limit)
 {
     int64_t r = kRedoPartItems / chunks;
+    if (limit > 0 && r > limit) r = limit;
     if (r < 1) r = 1;
     if (r > n_i) r = n_i > 0 ? n_i : 1;
     return (int32_t)r;
 }
 
-size_t redo_scratch_bytes(int32_t n_i, int64_t max_len)
+size_t redo_scratch_bytes(int32_t n_i, int64_t max_len, int32_t rcap_limit)
 {
     const int64_t rows = n_i > 0 ? n_i : 1;
     const int32_t C = redo_chunks_for(max_len);
-    const int64_t parts = (int64_t)redo_rcap_for(n_i, C) * C;
-    return 256 + 3 * round256((size_t)rows * sizeof(int32_t)) +
+    const int64_t parts = (int64_t)redo_rcap_for(n_i, C, rcap_limit) * C;
+    return 3 * round256((size_t)rows * sizeof(int32_t)) +
            round256((size_t)parts * 6 * sizeof(double));
 }
 
-void bind_redo_scratch(ForceArgs &a, void *base, int32_t groups, int64_t max_len)
+void bind_redo_scratch(ForceArgs &a, void *base, int32_t *counter, int32_t groups,
+                       int64_t max_len, int32_t rcap_limit)
 {
     char *p = (char *)base;
     const size_t arr = round256((size_t)(a.n_i > 0 ? a.n_i : 1) * sizeof(int32_t));
-    a.redo_count = (int32_t *)p;
-    a.redo_rows = (int32_t *)(p + 256);
-    a.redo_j0 = (int32_t *)(p + 256 + arr);
-    a.redo_j1 = (int32_t *)(p + 256 + 2 * arr);
-    a.redo_part = (double *)(p + 256 + 3 * arr);
+    a.redo_count = counter;
+    a.redo_rows = (int32_t *)p;
+    a.redo_j0 = (int32_t *)(p + arr);
+    a.redo_j1 = (int32_t *)(p + 2 * arr);
+    a.redo_part = (double *)(p + 3 * arr);
     a.redo_groups = groups;
     a.redo_chunks = redo_chunks_for(max_len);
-    a.redo_rcap = redo_rcap_for(a.n_i, a.redo_chunks);
+    a.redo_rcap = redo_rcap_for(a.n_i, a.redo_chunks, rcap_limit);
 }
 
 hipError_t launch_redo(const ForceArgs &a, hipStream_t s)

@@ -73,12 +73,16 @@ constexpr int64_t kRedoPartItems = int64_t(1) << 20;   // chunk partials held at
 
 // Components per slot: acc x,y,z, jerk x,y,z, and the two error-scale sums.
 constexpr int kSlotComp = 8;
-// Extra scratch for the redo list of n_i rows (counter, row / j-range arrays
-// and the chunk partials of 'groups' refinement work-groups).
+// Extra scratch for the redo list of n_i rows (row / j-range arrays and the
+// chunk partials); the counter is a separate word owned by the caller, so
+// that it outlives later reuse of the scratch.
 int32_t redo_groups_for(int cu_count);
-// max_len: longest j-range of any row of the launch
-size_t redo_scratch_bytes(int32_t n_i, int64_t max_len);
-void bind_redo_scratch(ForceArgs &a, void *base, int32_t groups, int64_t max_len);
+// max_len: longest j-range of any row of the launch.  rcap_limit > 0 bounds
+// the rows summed through chunk partials (the others are summed one
+// work-group per row, to the same bits), and with it the partials' bytes.
+size_t redo_scratch_bytes(int32_t n_i, int64_t max_len, int32_t rcap_limit = 0);
+void bind_redo_scratch(ForceArgs &a, void *base, int32_t *counter, int32_t groups,
+                       int64_t max_len, int32_t rcap_limit = 0);
 hipError_t launch_redo(const ForceArgs &a, hipStream_t s);
 
 struct Plan {

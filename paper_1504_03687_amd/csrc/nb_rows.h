@@ -32,6 +32,7 @@ struct Row {
     float rs2f;     // canonical radius
     float candf;    // FP32 candidate bound (mixed plan)
     int32_t i;      // body index, -1 when the lane has no row
+    int32_t jend;   // end of the j-range: staged bodies at or past it are padding
     int32_t cnt;    // neighbours found so far (true count)
     int32_t *lst;   // where this row's neighbours go
     int32_t lcap;   // capacity of lst
@@ -73,6 +74,7 @@ __device__ __forceinline__ void row_init(Row<MIXED> &R, const ForceArgs &a, int6
     R.candf = -1.0f;
     R.lst = nullptr;
     R.lcap = 0;
+    R.jend = 0;
     if (b >= row_end) return;
     const int64_t i = a.i_block[b];
     if (i < 0 || i >= a.n) return;   // bad index: handled in the epilogue / merge
@@ -106,6 +108,9 @@ __device__ __forceinline__ void rare_mixed(Row<MIXED> &R, const JBody &J, int32_
     int32_t jj = jidx;
     opaque(ex, ey, ez);
     opaque(jj);
+    // padding past the j-range (far away, mass 0) passes the test only for a
+    // huge or infinite radius; it is never a neighbour and adds nothing
+    if (jj >= R.jend) return;
     const bool self = jj == R.i;
     const bool nbr = (r2f < R.rs2f) && !self;
     if (nbr) {
@@ -127,6 +132,7 @@ __device__ __forceinline__ bool rare_f64(Row<MIXED> &R, int32_t jidx, double dx,
     int32_t jj = jidx;
     opaque(ex, ey, ez);
     opaque(jj);
+    if (jj >= R.jend) return false;   // padding: mass 0, its term is exactly zero
     const bool self = jj == R.i;
     const bool nbr = (canon_r2f(ex, ey, ez) < R.rs2f) && !self;
     if (nbr) {
@@ -267,7 +273,10 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTil
     const int tid = threadIdx.x;
     Row<MIXED> R[IR];
 #pragma unroll
-    for (int r = 0; r < IR; ++r) row_init(R[r], a, row0 + r * kBlock + tid, row_end, d, near);
+    for (int r = 0; r < IR; ++r) {
+        row_init(R[r], a, row0 + r * kBlock + tid, row_end, d, near);
+        R[r].jend = (int32_t)j1;
+    }
 
     // a wave none of whose lanes holds a valid row (the tail of a cluster's
     // last row tile) skips the pair loop; it still stages its share of every

@@ -63,6 +63,9 @@ struct nb_ctx {
     std::vector<hipEvent_t> free_events;
     double ms[NB_NCLASS] = {};
     int64_t launches[NB_NCLASS] = {};
+    // device words owned by the context for its whole life (never reallocated):
+    // [0] the refinement counter of nb_regular_force
+    int32_t *words = nullptr;
     int32_t *last_redo_counter = nullptr;   // device counter of the last mixed call
     // batched entry point: cached device metadata and graphs per shape
     std::vector<nbrt::BatchedCache *> batched;

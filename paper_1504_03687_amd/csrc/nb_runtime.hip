@@ -153,6 +153,17 @@ int nb_ctx_create(nb_ctx **out, int device, void *hip_stream)
             return NB_ERR_UNSUPPORTED;
         }
         ctx->cu_count = prop.multiProcessorCount;
+        // the context's own device words, allocated on its device
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        hipError_t e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipMalloc((void **)&ctx->words, 256);
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete ctx;
+            return NB_ERR_OOM;
+        }
         ctx->usable = true;
     }
     // device < 0: a host-only context that validates arguments and launches
@@ -177,6 +188,7 @@ int nb_ctx_destroy(nb_ctx *ctx)
         nbrt::batched_release(ctx);
         if (ctx->scratch) (void)hipFree(ctx->scratch);
         if (ctx->aux) (void)hipFree(ctx->aux);
+        if (ctx->words) (void)hipFree(ctx->words);
         for (auto &p : ctx->pending) {
             (void)hipEventDestroy(p.start);
             (void)hipEventDestroy(p.stop);
@@ -327,7 +339,7 @@ int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
         int rc = ensure_scratch(ctx, redo_bytes + slot_bytes);
         if (rc != NB_OK) return rc;
     }
-    if (redo_bytes) nb::bind_redo_scratch(fa, ctx->scratch, groups, n);
+    if (redo_bytes) nb::bind_redo_scratch(fa, ctx->scratch, ctx->words, groups, n);
     // the overflow word and the refinement counter start at zero (one launch)
     e = nb::launch_clear_words(overflow, redo_bytes ? fa.redo_count : nullptr, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e);

@@ -62,3 +62,62 @@ def test_binding_rejects_bad_tensors():
         compare_force(res, s["x"], s["v"], s["m"], host(ib), host(rs2), 8, TOL_FP64)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("batched", [False, True], ids=["single", "batched"])
+def test_bad_out_tensors_raise_before_launch(batched):
+    """Every caller-supplied output of a regular-force call is checked for
+    shape, dtype, device and contiguity: a wrong one raises ValueError and
+    nothing is written (the sentinel in the other outputs survives)."""
+    say(f"bad out tensors ({'batched' if batched else 'single'})")
+    c = nb.Context(0)
+    try:
+        s = W.small_state(33, 300)
+        x, v, m = dev(s["x"]), dev(s["v"]), dev(s["m"])
+        n_i, cap = 40, 16
+        ib = dev(np.arange(n_i, dtype=np.int32))
+        rs2 = dev(s["rs2"][:n_i])
+
+        def good():
+            return [torch.full((3, n_i), 7.0, dtype=torch.float64, device="cuda"),
+                    torch.full((3, n_i), 7.0, dtype=torch.float64, device="cuda"),
+                    torch.full((n_i,), 7, dtype=torch.int32, device="cuda"),
+                    torch.full((n_i, cap), 7, dtype=torch.int32, device="cuda"),
+                    torch.full((1,), 7, dtype=torch.int32, device="cuda")]
+
+        def call(out):
+            if batched:
+                return nb.regular_force_batched([0, 300], [0, n_i], x, v, m, ib, rs2, cap,
+                                                "mixed", out=out, ctx=c)
+            return nb.regular_force(x, v, m, ib, rs2, cap, "mixed", out=out, ctx=c)
+
+        bad_cases = [
+            (3, lambda t: t[:, : cap - 1].contiguous()),         # list one entry short
+            (3, lambda t: t[: n_i - 1].contiguous()),            # list one row short
+            (0, lambda t: t[:, :-1].contiguous()),               # acc one row short
+            (1, lambda t: t.float()),                            # jerk in FP32
+            (2, lambda t: t.to(torch.int64)),                    # count as int64
+            (4, lambda t: torch.zeros(2, dtype=torch.int32, device="cuda")),
+            (0, lambda t: t.cpu()),                              # host tensor
+            (3, lambda t: t.t().contiguous().t()),               # transposed view
+        ]
+        for k, mutate in bad_cases:
+            out = good()
+            out[k] = mutate(out[k])
+            with pytest.raises(ValueError):
+                call(out)
+            torch.cuda.synchronize()
+            for q, t in enumerate(out):
+                if q != k:
+                    assert bool((t == 7).all()), f"output {q} written after a bad output {k}"
+        with pytest.raises(ValueError):   # wrong number of outputs
+            call(good()[:4])
+        # the right outputs work
+        out = good()
+        res = call(out)
+        torch.cuda.synchronize()
+        assert res[0].data_ptr() == out[0].data_ptr()
+        compare_force(res, s["x"], s["v"], s["m"], np.arange(n_i, dtype=np.int32),
+                      s["rs2"][:n_i], cap, 5e-6)
+    finally:
+        c.close()

@@ -207,6 +207,31 @@ def test_edge_cases(ctx):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_huge_and_infinite_radius(ctx, prec):
+    """rs2 at or beyond the FP32 range (infinite after rounding): every other
+    body is a neighbour and the force is exactly zero.  Padding bodies of a
+    partial j-tile or past the end of a wave's j-range (far away, mass 0)
+    must not enter the lists, for any plan."""
+    say(f"huge radius {prec}")
+    n = 1000   # partial 256-body tiles and partial 64-body wave ranges
+    s = W.small_state(53, n, k_nn=16)
+    ib = np.array([0, 17, 999, 500, 3, 3], np.int32)
+    rs2 = np.array([np.inf, 1e300, 1e37, 3.5e38, s["rs2"][500], 0.0])
+    try:
+        for plan in ((1, 1, 1), (1, 2, 3), (2, 1, 1), (2, 4, 5), (0, 0, 0)):
+            ctx.set_plan(*plan)
+            for cap in (n, 100):
+                res = nb.regular_force(dev(s["x"]), dev(s["v"]), dev(s["m"]), dev(ib), dev(rs2),
+                                       cap, prec, ctx=ctx)
+                compare_force(res, s["x"], s["v"], s["m"], ib, rs2, cap, TOL[prec])
+                cnt = host(res[2])
+                assert list(cnt[:4]) == [n - 1] * 4, (plan, cnt)
+                assert not host(res[0])[:, :4].any() and not host(res[1])[:, :4].any()
+    finally:
+        ctx.set_plan(0, 0, 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_determinism_and_block_independence(ctx, prec):
     """A fixed plan gives bitwise-identical rows whatever else is in the block,
     and identical results on a re-run."""
