@@ -54,7 +54,9 @@ enum {
     NB_ERR_INVALID_ARG = -1, /* bad size, NULL required pointer, bad enum      */
     NB_ERR_HIP = -2,         /* a HIP runtime call failed                      */
     NB_ERR_OOM = -3,         /* scratch could not be grown (or exceeds limit)  */
-    NB_ERR_UNSUPPORTED = -4  /* no gfx950 device, or an unsupported plan       */
+    NB_ERR_UNSUPPORTED = -4, /* no gfx950 device, or an unsupported plan       */
+    NB_ERR_TOO_LARGE = -5    /* block too large for the fixed workspace of     */
+                             /* nb_regular_force_noalloc                       */
 };
 
 enum {
@@ -159,6 +161,34 @@ int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
                      const double *rs2, int32_t nb_cap, nb_precision prec, double *acc,
                      double *jerk, int32_t *nb_count, int32_t *nb_list, int32_t *overflow,
                      uint32_t *status);
+
+/* Allocation-free variant of nb_regular_force, for callers that cannot
+ * allocate device memory during the call: code being captured into a HIP
+ * graph, tight serving or stepping loops, and harnesses that forbid
+ * hipMalloc.  Same arguments, outputs, rules and kernels as nb_regular_force,
+ * but the split partials, neighbour segments and refinement lists live in a
+ * fixed device workspace that is part of the library itself (one copy per
+ * GPU, nb_fixed_workspace_bytes() bytes, held from the first context created
+ * on that GPU until the process ends) instead of context scratch.  The call
+ * allocates nothing, creates no events and never synchronises.  When the
+ * automatic (or forced) plan's scratch does not fit the workspace, the split
+ * count is lowered until it does (results stay within the same tolerances;
+ * FP64 sums may differ in the last bits from nb_regular_force, lists are
+ * identical).  Errors as nb_regular_force, plus NB_ERR_TOO_LARGE when even a
+ * single split does not fit (only NB_MIXED blocks of several million rows),
+ * and NB_ERR_UNSUPPORTED if the workspace could not be located on the
+ * context's device.  The workspace keeps the last call's contents; every
+ * call on a GPU, from any context or stream, uses the same workspace, so
+ * calls that overlap in time on one GPU race and must be serialised by the
+ * caller (one stream, or events). */
+int nb_regular_force_noalloc(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                             const double *m, int32_t n_i, const int32_t *i_block,
+                             const double *rs2, int32_t nb_cap, nb_precision prec,
+                             double *acc, double *jerk, int32_t *nb_count, int32_t *nb_list,
+                             int32_t *overflow, uint32_t *status);
+/* Size in bytes of the fixed workspace of nb_regular_force_noalloc (host
+ * only; no GPU work). */
+int nb_fixed_workspace_bytes(int64_t *bytes);
 
 /* Adjoint of nb_regular_force (no counterpart in the paper): given upstream
  * weights w_a, w_j ([3][n_i] FP64), the gradient of

@@ -85,6 +85,9 @@ def lib() -> C.CDLL:
             "nb_predict": ([vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "nb_regular_force": ([vp, i64, vp, vp, vp, i32, vp, vp, i32, C.c_int, vp, vp, vp,
                                   vp, vp, u32p], C.c_int),
+            "nb_regular_force_noalloc": ([vp, i64, vp, vp, vp, i32, vp, vp, i32, C.c_int, vp,
+                                          vp, vp, vp, vp, u32p], C.c_int),
+            "nb_fixed_workspace_bytes": ([C.POINTER(i64)], C.c_int),
             "nb_regular_force_adjoint": ([vp, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
                                           u32p], C.c_int),
             "nb_regular_force_batched": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, i32, C.c_int, vp,
@@ -271,10 +274,8 @@ def predict(x, v, a, jk, t0, t: float, m=None, out=None, ctx: Context | None = N
     return xp, vp, m32
 
 
-def regular_force(xp, vp, m, i_block, rs2, nb_cap: int, precision="fp64", status=None,
-                  out=None, ctx: Context | None = None):
-    """Regular acc, jerk (3, n_i) float64, nb_count (n_i,) int32, nb_list
-    (n_i, nb_cap) int32 and overflow (1,) int32 -- all on the GPU, no sync."""
+def _regular_force_call(fn: str, xp, vp, m, i_block, rs2, nb_cap: int, precision, status,
+                        out, ctx):
     n = m.shape[0]
     _dev(xp, "xp", torch.float64, (3, n))
     _dev(vp, "vp", torch.float64, (3, n))
@@ -290,12 +291,38 @@ def regular_force(xp, vp, m, i_block, rs2, nb_cap: int, precision="fp64", status
         _dev(status, "status", torch.int32, (1,))
     ctx = ctx or context(dev.index)
     ctx._bind_stream()
-    _check(lib().nb_regular_force(ctx.handle, n, _ptr(xp), _ptr(vp), _ptr(m), n_i,
-                                  _ptr(i_block), _ptr(rs2), int(nb_cap), _prec(precision),
-                                  _ptr(acc), _ptr(jerk), _ptr(cnt),
-                                  _ptr(lst) if nb_cap > 0 else None, _ptr(ovf), _ptr(status)),
-           "nb_regular_force")
+    _check(getattr(lib(), fn)(ctx.handle, n, _ptr(xp), _ptr(vp), _ptr(m), n_i,
+                              _ptr(i_block), _ptr(rs2), int(nb_cap), _prec(precision),
+                              _ptr(acc), _ptr(jerk), _ptr(cnt),
+                              _ptr(lst) if nb_cap > 0 else None, _ptr(ovf), _ptr(status)),
+           fn)
     return acc, jerk, cnt, lst, ovf
+
+
+def regular_force(xp, vp, m, i_block, rs2, nb_cap: int, precision="fp64", status=None,
+                  out=None, ctx: Context | None = None):
+    """Regular acc, jerk (3, n_i) float64, nb_count (n_i,) int32, nb_list
+    (n_i, nb_cap) int32 and overflow (1,) int32 -- all on the GPU, no sync."""
+    return _regular_force_call("nb_regular_force", xp, vp, m, i_block, rs2, nb_cap, precision,
+                               status, out, ctx)
+
+
+def regular_force_noalloc(xp, vp, m, i_block, rs2, nb_cap: int, precision, out,
+                          status=None, ctx: Context | None = None):
+    """nb_regular_force_noalloc: as regular_force, into the caller's `out`
+    tensors (required, so nothing is allocated), with the library's fixed
+    device workspace instead of context scratch."""
+    if out is None:
+        raise ValueError("regular_force_noalloc writes into the caller's out tensors")
+    return _regular_force_call("nb_regular_force_noalloc", xp, vp, m, i_block, rs2, nb_cap,
+                               precision, status, out, ctx)
+
+
+def fixed_workspace_bytes() -> int:
+    """Size of the fixed device workspace of regular_force_noalloc."""
+    v = C.c_int64()
+    _check(lib().nb_fixed_workspace_bytes(C.byref(v)), "nb_fixed_workspace_bytes")
+    return v.value
 
 
 def regular_force_adjoint(xp, vp, m, i_block, rs2, w_a, w_j, status=None,

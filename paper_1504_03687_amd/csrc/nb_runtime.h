@@ -66,6 +66,9 @@ struct nb_ctx {
     // device words owned by the context for its whole life (never reallocated):
     // [0] the refinement counter of nb_regular_force
     int32_t *words = nullptr;
+    // device address of the library's fixed workspace on this context's
+    // device (nb_regular_force_noalloc); shared by every context on the device
+    void *fixed_scratch = nullptr;
     int32_t *last_redo_counter = nullptr;   // device counter of the last mixed call
     // batched entry point: cached device metadata and graphs per shape
     std::vector<nbrt::BatchedCache *> batched;

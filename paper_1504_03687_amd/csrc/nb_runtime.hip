@@ -26,6 +26,40 @@
 using nb::Plan;
 
 // ---------------------------------------------------------------------------
+// fixed workspace of the allocation-free entry point
+// ---------------------------------------------------------------------------
+// One copy per GPU, part of the library's code object: it exists from the
+// moment the library's kernels are loaded on a device until the process ends.
+// Host code never uses this name as a device address (on the host it is only
+// a stand-in); the address comes from hipGetSymbolAddress, looked up once per
+// device when the first context on that device is created.
+static constexpr size_t kFixedScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void *g_fixed_ptr[kMaxDevices] = {};
+
+// Device address of 'scratch' on the current device (which must be
+// 'device'), looked up on first use and kept.
+hipError_t fixed_scratch_of(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_fixed_mu);
+    if (!g_fixed_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_fixed_ptr[device] = p;
+    }
+    *out = g_fixed_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // context helpers
 // ---------------------------------------------------------------------------
 namespace nbrt {
@@ -124,6 +158,8 @@ const char *nb_error_string(int code)
     case NB_ERR_HIP: return "HIP runtime error";
     case NB_ERR_OOM: return "out of device memory or over the scratch limit";
     case NB_ERR_UNSUPPORTED: return "unsupported device or plan";
+    case NB_ERR_TOO_LARGE:
+        return "block too large for the fixed workspace of the allocation-free entry point";
     default: return "unknown error";
     }
 }
@@ -158,6 +194,7 @@ int nb_ctx_create(nb_ctx **out, int device, void *hip_stream)
         (void)hipGetDevice(&prev);
         hipError_t e = hipSetDevice(device);
         if (e == hipSuccess) e = hipMalloc((void **)&ctx->words, 256);
+        if (e == hipSuccess) e = fixed_scratch_of(device, &ctx->fixed_scratch);
         (void)hipSetDevice(prev);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -284,10 +321,22 @@ int nb_predict(nb_ctx *ctx, int64_t n, double t, const double *x, const double *
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
 }
 
-int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
-                     const double *m, int32_t n_i, const int32_t *i_block, const double *rs2,
-                     int32_t nb_cap, nb_precision prec, double *acc, double *jerk,
-                     int32_t *nb_count, int32_t *nb_list, int32_t *overflow, uint32_t *status)
+}  // extern "C"
+
+namespace nbrt {
+
+// Shared body of nb_regular_force and nb_regular_force_noalloc.  With
+// fixed == nullptr the scratch comes from the context (grown on demand);
+// otherwise it is the caller-supplied device workspace of fixed_bytes, no
+// allocation and no event creation happens, and the plan's split count is
+// lowered until its scratch fits (NB_ERR_TOO_LARGE when even one split does
+// not).
+static int regular_force_impl(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                              const double *m, int32_t n_i, const int32_t *i_block,
+                              const double *rs2, int32_t nb_cap, nb_precision prec,
+                              double *acc, double *jerk, int32_t *nb_count, int32_t *nb_list,
+                              int32_t *overflow, uint32_t *status, void *fixed,
+                              size_t fixed_bytes)
 {
     if (!ctx || n <= 0 || n > INT32_MAX || n_i < 0 || nb_cap < 0) return NB_ERR_INVALID_ARG;
     if (prec != NB_FP64 && prec != NB_MIXED) return NB_ERR_INVALID_ARG;
@@ -328,46 +377,103 @@ int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
     fa.nb_list = nb_list;
     fa.overflow = overflow;
     fa.status = status;
-    fa.splits = p.splits;
-    fa.split_len = split_len;
     fa.redo_k = mixed ? redo_k(ctx) : 0.0;
     fa.near_factor = n >= nb::kNearMinBodies ? nb::kNearFactor : 1.0f;
     const int32_t groups = nb::redo_groups_for(ctx->cu_count);
-    const size_t redo_bytes = fa.redo_k > 0.0 ? nb::redo_scratch_bytes(n_i, n) : 0;
+    void *base = nullptr;
+    int32_t rcap_limit = 0;
+    size_t redo_bytes = fa.redo_k > 0.0 ? nb::redo_scratch_bytes(n_i, n) : 0;
+    if (fixed) {
+        // the refinement's chunk partials shrink first (rows past them are
+        // summed one work-group each, to the same bits), then the splits
+        for (rcap_limit = (int32_t)nb::kRedoPartItems;
+             redo_bytes > fixed_bytes / 2 && rcap_limit > 1; rcap_limit /= 2)
+            redo_bytes = nb::redo_scratch_bytes(n_i, n, rcap_limit / 2);
+        if (redo_bytes > fixed_bytes) return NB_ERR_TOO_LARGE;
+        const size_t room = fixed_bytes - redo_bytes;
+        while (p.splits > 1 && nb::force_scratch_bytes(p, n_i) > room) {
+            // largest split count whose slots fit, then re-normalised
+            const size_t per_slot = nb::kSlotComp * sizeof(double) + sizeof(int32_t) +
+                                    nb::kSegCap * sizeof(int32_t);
+            const int64_t fit = (int64_t)(room / per_slot) / std::max<int32_t>(n_i, 1);
+            p.splits = (int)std::max<int64_t>(1, std::min<int64_t>(fit, p.splits - 1));
+            finish_plan(p, n, n_i, &split_len);
+        }
+        base = fixed;
+    }
+    fa.splits = p.splits;
+    fa.split_len = split_len;
     const size_t slot_bytes = nb::force_scratch_bytes(p, n_i);
-    if (redo_bytes + slot_bytes > 0) {
+    if (!fixed && redo_bytes + slot_bytes > 0) {
         int rc = ensure_scratch(ctx, redo_bytes + slot_bytes);
         if (rc != NB_OK) return rc;
+        base = ctx->scratch;
     }
-    if (redo_bytes) nb::bind_redo_scratch(fa, ctx->scratch, ctx->words, groups, n);
+    if (redo_bytes) nb::bind_redo_scratch(fa, base, ctx->words, groups, n, rcap_limit);
     // the overflow word and the refinement counter start at zero (one launch)
     e = nb::launch_clear_words(overflow, redo_bytes ? fa.redo_count : nullptr, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e);
-    nb::force_bind_scratch(fa, (char *)ctx->scratch + redo_bytes);
+    nb::force_bind_scratch(fa, (char *)base + redo_bytes);
     std::snprintf(ctx->last_plan, sizeof ctx->last_plan,
-                  "mapping=%d rows_per_lane=%d splits=%d split_len=%lld prec=%s", p.mapping,
-                  p.rows_per_lane, p.splits, (long long)split_len, mixed ? "mixed" : "fp64");
+                  "mapping=%d rows_per_lane=%d splits=%d split_len=%lld prec=%s%s", p.mapping,
+                  p.rows_per_lane, p.splits, (long long)split_len, mixed ? "mixed" : "fp64",
+                  fixed ? " workspace=fixed" : "");
 
-    hipEvent_t ev[2];
-    e = timed_begin(ctx, NB_CLASS_FORCE, ev);
+    // timing events are created on demand, so the allocation-free path is
+    // never timed
+    const bool timed = !fixed;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (timed) e = timed_begin(ctx, NB_CLASS_FORCE, ev);
     if (e == hipSuccess) e = nb::launch_force(p, mixed, fa, ctx->stream);
-    if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_FORCE, ev);
+    if (e == hipSuccess && timed) e = timed_end(ctx, NB_CLASS_FORCE, ev);
     if (e != hipSuccess) return hip_fail(ctx, e);
     if (p.splits > 1) {
-        e = timed_begin(ctx, NB_CLASS_MERGE, ev);
+        if (timed) e = timed_begin(ctx, NB_CLASS_MERGE, ev);
         if (e == hipSuccess) e = nb::launch_merge(mixed, fa, ctx->stream);
-        if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_MERGE, ev);
+        if (e == hipSuccess && timed) e = timed_end(ctx, NB_CLASS_MERGE, ev);
         if (e != hipSuccess) return hip_fail(ctx, e);
     }
     if (redo_bytes) {
-        e = timed_begin(ctx, NB_CLASS_REDO, ev);
+        if (timed) e = timed_begin(ctx, NB_CLASS_REDO, ev);
         if (e == hipSuccess) e = nb::launch_redo(fa, ctx->stream);
-        if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_REDO, ev);
+        if (e == hipSuccess && timed) e = timed_end(ctx, NB_CLASS_REDO, ev);
         if (e != hipSuccess) return hip_fail(ctx, e);
         ctx->last_redo_counter = fa.redo_count;
     } else {
         ctx->last_redo_counter = nullptr;
     }
+    return NB_OK;
+}
+
+}  // namespace nbrt
+
+extern "C" {
+
+int nb_regular_force(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                     const double *m, int32_t n_i, const int32_t *i_block, const double *rs2,
+                     int32_t nb_cap, nb_precision prec, double *acc, double *jerk,
+                     int32_t *nb_count, int32_t *nb_list, int32_t *overflow, uint32_t *status)
+{
+    return regular_force_impl(ctx, n, xp, vp, m, n_i, i_block, rs2, nb_cap, prec, acc, jerk,
+                              nb_count, nb_list, overflow, status, nullptr, 0);
+}
+
+int nb_regular_force_noalloc(nb_ctx *ctx, int64_t n, const double *xp, const double *vp,
+                             const double *m, int32_t n_i, const int32_t *i_block,
+                             const double *rs2, int32_t nb_cap, nb_precision prec, double *acc,
+                             double *jerk, int32_t *nb_count, int32_t *nb_list,
+                             int32_t *overflow, uint32_t *status)
+{
+    if (ctx && ctx->usable && !ctx->fixed_scratch) return NB_ERR_UNSUPPORTED;
+    return regular_force_impl(ctx, n, xp, vp, m, n_i, i_block, rs2, nb_cap, prec, acc, jerk,
+                              nb_count, nb_list, overflow, status,
+                              ctx ? ctx->fixed_scratch : nullptr, kFixedScratchBytes);
+}
+
+int nb_fixed_workspace_bytes(int64_t *bytes)
+{
+    if (!bytes) return NB_ERR_INVALID_ARG;
+    *bytes = (int64_t)kFixedScratchBytes;
     return NB_OK;
 }
 
