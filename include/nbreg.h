@@ -47,7 +47,15 @@ extern "C" {
 
 typedef struct nb_ctx nb_ctx;
 
-typedef enum { NB_FP64 = 0, NB_MIXED = 1 } nb_precision;
+typedef enum {
+    NB_FP64 = 0,
+    NB_MIXED = 1,
+    /* range markers only: they make every int a representable nb_precision,
+     * so an out-of-range value passed through the ABI is a checked argument
+     * error (NB_ERR_INVALID_ARG), not undefined behaviour in the library */
+    NB_PRECISION_RANGE_MIN_ = -2147483647 - 1,
+    NB_PRECISION_RANGE_MAX_ = 2147483647
+} nb_precision;
 
 enum {
     NB_OK = 0,
