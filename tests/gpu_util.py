@@ -45,19 +45,28 @@ def check_lists(cnt, lst, ocnt, olst, cap):
             raise AssertionError(f"list of row {b} differs: {lst[b, :k][:8]} vs {olst[b, :k][:8]}")
 
 
-def compare_force(res, xp, vp, m, i_block, rs2, cap, tol, rows=None):
-    """res: tuple from paper_1504_03687_amd.regular_force (GPU tensors).
-    Compares all rows (or the given subset) with the oracle; returns max errors."""
-    acc, jerk, cnt, lst, ovf = (host(t) for t in res)
+def oracle_rows(xp, vp, m, i_block, rs2, cap, rows=None):
+    """The oracle's regular force for all rows of a block (or a subset);
+    pass the result to compare_force(ref=...) to check several GPU results
+    against one oracle run."""
     ib = np.asarray(i_block)
     r2 = np.asarray(rs2)
     sel = np.arange(ib.size) if rows is None else np.asarray(rows)
-    oa, oj, oc, ol, oo, obad = oracle.regular(xp, vp, m, ib[sel], r2[sel], cap)
+    return sel, oracle.regular(xp, vp, m, ib[sel], r2[sel], cap)
+
+
+def compare_force(res, xp, vp, m, i_block, rs2, cap, tol, rows=None, ref=None):
+    """res: tuple from paper_1504_03687_amd.regular_force (GPU tensors).
+    Compares all rows (or the given subset) with the oracle; returns max errors.
+    ref: a precomputed oracle_rows(...) result for the same rows."""
+    acc, jerk, cnt, lst, ovf = (host(t) for t in res)
+    sel, (oa, oj, oc, ol, oo, obad) = (
+        ref if ref is not None else oracle_rows(xp, vp, m, i_block, rs2, cap, rows))
     check_lists(cnt[sel], lst[sel] if cap > 0 else lst, oc, ol, cap)
     ea = row_rel_err(acc[:, sel], oa)
     ej = row_rel_err(jerk[:, sel], oj)
     assert ea.max() <= tol, f"acc error {ea.max():.3e} > {tol} at row {sel[ea.argmax()]}"
     assert ej.max() <= tol, f"jerk error {ej.max():.3e} > {tol} at row {sel[ej.argmax()]}"
-    if rows is None:
-        assert int(ovf[0]) == int(oo)
+    if sel.size == acc.shape[1] and np.array_equal(sel, np.arange(sel.size)):
+        assert int(ovf[0]) == int(oo)   # every row checked: the overflow word too
     return float(ea.max()), float(ej.max())

@@ -74,21 +74,27 @@ def test_adjoint_bad_index_and_empty(ctx):
 
 
 def test_adjoint_n65536(ctx):
-    """N = 65536 Plummer + Kroupa: the 1024-row subset against the oracle's
-    gradient, and the all-active block against central differences (h = 1e-6)
-    of local losses at sampled bodies."""
+    """N = 65536 Plummer + Kroupa, all bodies active: the whole gradient
+    against the oracle's, body by body; a 1024-row subset the same way; and
+    the all-active gradient against central differences (h = 1e-6) of local
+    losses at 256 bodies (the 32 most central and 224 random ones)."""
     s = W.adjoint_plummer_n65536()
     x, v, m = s["x"], s["v"], s["m"]
+    ib, rs2, wa, wj = s["i_block"], s["rs2"], s["w_a"], s["w_j"]
+    say("adjoint N=65536 full block vs the oracle gradient")
+    _check_vs_oracle(ctx, x, v, m, ib, rs2, wa, wj)
     say("adjoint N=65536 subset")
     sub = np.random.default_rng(5).choice(s["n"], 1024, replace=False).astype(np.int32)
     _check_vs_oracle(ctx, x, v, m, sub, s["rs2"][sub], s["w_a"][:, sub], s["w_j"][:, sub])
     say("adjoint N=65536 full block vs finite differences")
-    ib, rs2, wa, wj = s["i_block"], s["rs2"], s["w_a"], s["w_j"]
     gx, gv, gm = (host(t) for t in nb.regular_force_adjoint(
         dev(x), dev(v), dev(m), dev(ib), dev(rs2), dev(wa), dev(wj), ctx=ctx))
     r = np.sqrt((x ** 2).sum(0))
     rng = np.random.default_rng(55)
-    bodies = np.unique(np.concatenate([np.argsort(r)[:24], rng.choice(s["n"], 40, replace=False)]))
+    central = np.argsort(r)[:32]
+    others = rng.choice(np.setdiff1d(np.arange(s["n"]), central), 224, replace=False)
+    bodies = np.concatenate([central, others])
+    assert np.unique(bodies).size == 256
     h = 1e-6
     worst = 0.0
     for k in bodies:

@@ -11,7 +11,7 @@ import torch
 import oracle
 import paper_1504_03687_amd as nb
 import workloads as W
-from gpu_util import (TOL_FP64, TOL_MIXED, check_lists, compare_force, dev, host, row_rel_err,
+from gpu_util import (TOL_FP64, TOL_MIXED, oracle_rows, check_lists, compare_force, dev, host, row_rel_err,
                       say)
 
 pytestmark = pytest.mark.gpu
@@ -271,40 +271,47 @@ def test_power_of_two_scaling_fp64(ctx):
     assert np.array_equal(sc[0], base[0] / 4) and np.array_equal(sc[1], base[1] / 8)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_plummer_kroupa_n131072_blocks(ctx, prec):
+def test_plummer_kroupa_n131072_blocks(ctx):
     """N = 131072 Plummer + Kroupa: random blocks of 1, 32, 1024, 16384 rows
-    in full and the all-active block on 512 sampled rows."""
+    and the all-active block, every row of each against the oracle, in both
+    precisions (one oracle run per block)."""
     s = W.plummer_kroupa_n131072()
     xp, vp, _ = _predict_dev(ctx, s)
     ox, ov = oracle.predict(s["t"], s["x"], s["v"], s["a"], s["jk"], s["t0"])
     assert np.array_equal(host(xp), ox)
     m = dev(s["m"])
     for size, blk in s["blocks"].items():
-        say(f"plummer-kroupa N=131072 {prec} n_i={size}")
         rs2 = s["rs2"][blk]
-        res = nb.regular_force(xp, vp, m, dev(blk), dev(rs2), s["nb_cap"], prec, ctx=ctx)
-        rows = None if size <= 16384 else np.random.default_rng(size).choice(size, 512,
-                                                                             replace=False)
-        ea, ej = compare_force(res, ox, ov, s["m"], blk, rs2, s["nb_cap"], TOL[prec], rows=rows)
-        say(f"  plan {ctx.last_plan()}  err acc {ea:.2e} jerk {ej:.2e}")
+        say(f"plummer-kroupa N=131072 n_i={size}: oracle on all {blk.size} rows")
+        ref = oracle_rows(ox, ov, s["m"], blk, rs2, s["nb_cap"])
+        for prec in ("mixed", "fp64"):
+            res = nb.regular_force(xp, vp, m, dev(blk), dev(rs2), s["nb_cap"], prec, ctx=ctx)
+            ea, ej = compare_force(res, ox, ov, s["m"], blk, rs2, s["nb_cap"], TOL[prec],
+                                   ref=ref)
+            say(f"  {prec} plan {ctx.last_plan()}  err acc {ea:.2e} jerk {ej:.2e}")
+            del res
 
 
-def _million_body_sample_rows(s, blk, k=384):
-    """Rows of block blk to check: the most central bodies, binary components
-    and a random remainder."""
+def _million_body_sample_rows(s, blk, k=4096):
+    """Rows of block blk to check against the oracle: the 64 most central
+    bodies, up to 1024 binary components, and a random remainder up to k."""
     r = np.sqrt((s["x"] ** 2).sum(0))[blk]
     central = np.argsort(r)[:64]
-    binaries = np.nonzero(blk < 2 * s["n_bin"])[0][:64]
+    comp = np.nonzero(blk < 2 * s["n_bin"])[0]
     rng = np.random.default_rng(3)
-    rest = rng.choice(blk.size, min(k, blk.size), replace=False)
-    return np.unique(np.concatenate([central, binaries, rest]))[:k + 128]
+    binaries = rng.choice(comp, min(1024, comp.size), replace=False)
+    chosen = np.unique(np.concatenate([central, binaries]))
+    rest = np.setdiff1d(np.arange(blk.size), chosen)
+    extra = rng.choice(rest, max(0, min(k - chosen.size, rest.size)), replace=False)
+    return np.unique(np.concatenate([chosen, extra]))
 
 
 @pytest.mark.parametrize("level", [3, 12])
 def test_million_body_cluster(ctx, level):
     """N = 2^20 Plummer + Kroupa with 5% binaries, both precisions, at the full
-    block (level 3) and a deep block level; sampled rows vs the oracle."""
+    block (level 3) and a deep block level: 4096 rows against the oracle (the
+    64 most central bodies, 1024 binary components, random others), counts
+    and lists of every row equal across the two precisions."""
     s = W.binary_cluster_n1m()
     t, t0, blk = W.binary_cluster_level(s, level)
     say(f"N=2^20 cluster level {level}: n_i={blk.size}")
@@ -313,16 +320,22 @@ def test_million_body_cluster(ctx, level):
     ox, ov = oracle.predict(t, s["x"], s["v"], s["a"], s["jk"], t0)
     assert np.array_equal(host(xp), ox) and np.array_equal(host(vp), ov)
     rows = _million_body_sample_rows(s, blk)
+    n_bin_rows = int((blk[rows] < 2 * s["n_bin"]).sum())
+    say(f"  oracle on {rows.size} rows ({n_bin_rows} binary components)")
+    assert rows.size >= min(4096, blk.size) and n_bin_rows >= min(1024, int(
+        (blk < 2 * s["n_bin"]).sum()))
     m = dev(s["m"])
     rs2 = s["rs2"][blk]
+    ref = oracle_rows(ox, ov, s["m"], blk, rs2, s["nb_cap"], rows)
     keep = {}
     for prec in ("mixed", "fp64"):
         res = nb.regular_force(xp, vp, m, dev(blk), dev(rs2), s["nb_cap"], prec, ctx=ctx)
-        ea, ej = compare_force(res, ox, ov, s["m"], blk, rs2, s["nb_cap"], TOL[prec], rows=rows)
+        ea, ej = compare_force(res, ox, ov, s["m"], blk, rs2, s["nb_cap"], TOL[prec], ref=ref)
         say(f"  {prec} plan {ctx.last_plan()}  err acc {ea:.2e} jerk {ej:.2e}")
         keep[prec] = res
-    # every row: the FP64 kernel is within 1e-12 of the oracle on the sample,
-    # so mixed within 5e-6 - 1e-12 of FP64 on every row keeps the mixed bar
+    # every row: counts and lists are the same in both precisions (the lists
+    # of the sampled rows are the oracle's, above); forces of the two
+    # precisions agree within the mixed bar on every row
     mx, fp = keep["mixed"], keep["fp64"]
     assert torch.equal(mx[2], fp[2])
     cap = s["nb_cap"]
