@@ -33,6 +33,19 @@ sys.path.insert(0, ROOT)
 # r.u (5), 1/sqrt (1), r^-2 (1), m r^-3 (2), 3 (r.u) r^-2 (2), acc += m r^-3 r
 # (6), jerk += m r^-3 (u - alpha r) (12).
 FLOPS_PER_PAIR = 40
+# Algorithmic floating-point operations per pair of the adjoint's two FP64
+# recompute passes (FMA = 2), counted from the gradient formulas with the
+# row-constant weights A = w_a, B = w_j factored out of the pair loops:
+#  row pass: r, u differences 6, |r|^2 5, 1/sqrt 1, |r|^-2, |r|^-3, |r|^-5 3,
+#    r.u, A.r, B.r, B.u 20, m |r|^-5 and its (B.r) product 2, the r
+#    coefficient 6, sum m |r|^-3 2, sum m |r|^-5 (r.u) 2, the u and r sums
+#    of H 12, sum (B.r) r 6 -> 65;
+#  body pass: the same geometry 35, A.r + B.u and s (B.r) 2, the two mass
+#    sums 4, |r|^-5 s and |r|^-5 (B.r) 2, the r coefficient 4, the A, B and
+#    u/r sums 36 -> 83.
+ADJ_FLOPS_ROWS = 65
+ADJ_FLOPS_BODIES = 83
+
 # MI355X published vector peaks (TFLOP/s): FP32 157.3 (with packed FP32
 # instructions), FP64 78.6.  256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz =
 # 78.6 TFLOP/s is also the ceiling of unpacked FP32.
@@ -97,6 +110,137 @@ def steady_ms(call, warm_ms=30.0, time_ms=50.0, min_reps=3):
         call()
     torch.cuda.synchronize()
     return (time.perf_counter() - c1) * 1e3 / reps
+
+
+def cpu_model() -> str:
+    """Host CPU model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def adjoint_leg(nb, W, ctx, dev):
+    """Adjoint of the regular force at N = 65536 Plummer + Kroupa, all bodies
+    active, FP64, in steady state; roofline by the algorithmic flops of both
+    passes over the whole call's time."""
+    s5 = W.adjoint_plummer_n65536()
+    n5 = s5["n"]
+    a5 = [dev(s5[k]) for k in ("x", "v", "m", "i_block", "rs2", "w_a", "w_j")]
+    ms = steady_ms(lambda: nb.regular_force_adjoint(*a5, ctx=ctx))
+    pp = float(n5) * (n5 - 1)
+    ach = (ADJ_FLOPS_ROWS + ADJ_FLOPS_BODIES) * pp / ms * 1e-9
+    log(f"adjoint: {ms:.2f} ms, {ach:.1f} TFLOP/s")
+    return {"workload": f"N={n5} Plummer+Kroupa, all active, FP64",
+            "ms": round(ms, 3), "gpairs_per_s_per_pass": round(pp / ms * 1e-6, 2),
+            "roofline": {"bound": "alu", "achieved": round(ach, 2), "peak": PEAK_FP64,
+                         "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64, 4),
+                         "flops_per_pair": {"row_pass": ADJ_FLOPS_ROWS,
+                                            "body_pass": ADJ_FLOPS_BODIES},
+                         "time": "whole call (both passes and their reductions)"}}
+
+
+def small_configs_leg(nb, W, ctx, dev, precs):
+    """GPU rates of the smaller workloads, in steady state (predict + regular
+    force per call): N = 1024 equal-mass Plummer, all active, nb_cap 256; and
+    N = 131072 Plummer + Kroupa with random blocks of 1, 32, 1024, 16384 and
+    131072 rows, nb_cap 512."""
+    import torch
+    out = {}
+    s1 = W.plummer_equal_n1024()
+    s2 = W.plummer_kroupa_n131072()
+    for name, s, blocks in (("plummer_equal_n1024", s1, {1024: s1["i_block"]}),
+                            ("plummer_kroupa_n131072", s2, s2["blocks"])):
+        x, v, a, jk, t0 = (dev(s[k]) for k in ("x", "v", "a", "jk", "t0"))
+        m = dev(s["m"])
+        xp = torch.empty_like(x)
+        vp = torch.empty_like(v)
+        n = s["n"]
+        ent = {}
+        for size, blk in blocks.items():
+            bd, rd = dev(blk), dev(s["rs2"][blk])
+            row = {}
+            for prec in precs:
+                o = nb.regular_force(x, v, m, bd, rd, s["nb_cap"], prec, ctx=ctx)
+
+                def call():
+                    nb.predict(x, v, a, jk, t0, s["t"], out=(xp, vp), ctx=ctx)
+                    nb.regular_force(xp, vp, m, bd, rd, s["nb_cap"], prec, out=o, ctx=ctx)
+                ms = steady_ms(call)
+                row[prec] = {"ms": round(ms, 4),
+                             "gpairs_per_s": round(blk.size * (n - 1) / ms * 1e-6, 2),
+                             "plan": ctx.last_plan()}
+                del o
+            ent[str(size)] = row
+            log(f"{name} n_i={size}: " + " ".join(
+                f"{p}={row[p]['gpairs_per_s']} G/s" for p in precs))
+        out[name] = ent
+    return out
+
+
+def oracle_leg(W, threads):
+    """The CPU oracle (plain FP64 C, OpenMP over rows) on the other workloads,
+    in full: N = 1024 all active; N = 131072 blocks of 1 .. 131072 rows; the
+    256-cluster ensemble cluster by cluster; the N = 65536 adjoint."""
+    import oracle
+    res = {}
+
+    def timed(fn):
+        c1 = time.perf_counter()
+        fn()
+        return time.perf_counter() - c1
+
+    s1 = W.plummer_equal_n1024()
+    ox, ov = oracle.predict(s1["t"], s1["x"], s1["v"], s1["a"], s1["jk"], s1["t0"])
+    p1 = 1024.0 * 1023
+    dt = timed(lambda: oracle.regular(ox, ov, s1["m"], s1["i_block"], s1["rs2"], 256))
+    res["plummer_equal_n1024"] = {"pairs": p1, "s": round(dt, 3),
+                                  "gpairs_per_s": round(p1 / dt * 1e-9, 4)}
+    s2 = W.plummer_kroupa_n131072()
+    ox, ov = oracle.predict(s2["t"], s2["x"], s2["v"], s2["a"], s2["jk"], s2["t0"])
+    n2 = s2["n"]
+    p2, dt = 0.0, 0.0
+    for blk in s2["blocks"].values():
+        dt += timed(lambda: oracle.regular(ox, ov, s2["m"], blk, s2["rs2"][blk], 512))
+        p2 += blk.size * (n2 - 1.0)
+    res["plummer_kroupa_n131072_all_blocks"] = {"pairs": p2, "s": round(dt, 3),
+                                                "gpairs_per_s": round(p2 / dt * 1e-9, 4)}
+    log(f"oracle: N=131072 blocks {p2:.3g} pairs in {dt:.1f}s")
+    s4 = W.cluster_ensemble_256()
+    ox, ov = oracle.predict(s4["t"], s4["x"], s4["v"], s4["a"], s4["jk"], s4["t0"])
+    p4, dt = 0.0, 0.0
+    for c in range(len(s4["j_off"]) - 1):
+        j0, j1 = s4["j_off"][c], s4["j_off"][c + 1]
+        r0, r1 = s4["i_off"][c], s4["i_off"][c + 1]
+        ib = (s4["i_block"][r0:r1] - j0).astype(np.int32)
+        dt += timed(lambda: oracle.regular(ox[:, j0:j1], ov[:, j0:j1], s4["m"][j0:j1], ib,
+                                           s4["rs2"][r0:r1], s4["nb_cap"]))
+        p4 += (r1 - r0) * float(j1 - j0)
+    res["cluster_ensemble_256"] = {"pairs": p4, "s": round(dt, 3),
+                                   "gpairs_per_s": round(p4 / dt * 1e-9, 4)}
+    log(f"oracle: ensemble {p4:.3g} pairs in {dt:.1f}s")
+    s5 = W.adjoint_plummer_n65536()
+    n5 = s5["n"]
+    dt = timed(lambda: oracle.adjoint(s5["x"], s5["v"], s5["m"], s5["i_block"], s5["rs2"],
+                                      s5["w_a"], s5["w_j"]))
+    p5 = float(n5) * (n5 - 1)
+    res["adjoint_plummer_n65536"] = {"pairs_per_pass": p5, "s": round(dt, 3),
+                                     "gpairs_per_s_per_pass": round(p5 / dt * 1e-9, 4)}
+    log(f"oracle: adjoint {dt:.1f}s")
+    res["threads"] = threads
+    return res
 
 
 def sched_leg(nb, W, s, ctx, dev, reps=20):
@@ -259,8 +403,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--cpu-rows", type=int, default=12288,
+    ap.add_argument("--cpu-rows", type=int, default=16384,
                     help="rows of the full block timed on the CPU oracle (0 = skip)")
+    ap.add_argument("--no-oracle-configs", action="store_true",
+                    help="skip timing the CPU oracle on the other workloads")
     ap.add_argument("--no-levels", action="store_true")
     ap.add_argument("--only", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--step-only", action="store_true",
@@ -269,6 +415,9 @@ def main():
     ap.add_argument("--sched-only", action="store_true",
                     help="only time the block-step scheduler on the same cluster's levels "
                          "and print its figures (used for kernel profiles)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only time the adjoint at N = 65536 (all active, FP64) and print "
+                         "its figures (used for kernel profiles)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (FP64 elementwise kernel) "
                          "and print its bandwidth; used to scale rocprofv3 byte counters")
@@ -300,6 +449,10 @@ def main():
     import workloads as W
 
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    if args.adjoint_only:
+        ctx = nb.Context(0)
+        print(json.dumps({"adjoint": adjoint_leg(nb, W, ctx, dev)}), flush=True)
+        return
     t_gen = time.time()
     s = W.binary_cluster_n1m(args.n)
     n = s["n"]
@@ -414,14 +567,7 @@ def main():
     # (256 clusters, one graph launch), each timed in steady state
     extras = {}
     if not args.no_levels:
-        s5 = W.adjoint_plummer_n65536()
-        n5 = s5["n"]
-        a5 = [dev(s5[k]) for k in ("x", "v", "m", "i_block", "rs2", "w_a", "w_j")]
-        ms = steady_ms(lambda: nb.regular_force_adjoint(*a5, ctx=ctx))
-        extras["adjoint"] = {"workload": f"N={n5} Plummer+Kroupa, all active, FP64",
-                             "ms": round(ms, 3),
-                             "gpairs_per_s_per_pass": round(n5 * (n5 - 1) / ms * 1e-6, 2)}
-        log(f"adjoint: {ms:.2f} ms")
+        extras["adjoint"] = adjoint_leg(nb, W, ctx, dev)
         s4 = W.cluster_ensemble_256()
         xp4, vp4, _ = nb.predict(dev(s4["x"]), dev(s4["v"]), dev(s4["a"]), dev(s4["jk"]),
                                  dev(s4["t0"]), s4["t"], ctx=ctx)
@@ -431,22 +577,37 @@ def main():
         rows = np.diff(s4["i_off"])
         pairs4 = float((sizes * rows).sum())
         for prec in precs:
+            # the default shape rule first, then the shape the batched tuner
+            # picks for this ensemble
             o4 = nb.regular_force_batched(*b4, s4["nb_cap"], prec, ctx=ctx)
             ms = steady_ms(
                 lambda: nb.regular_force_batched(*b4, s4["nb_cap"], prec, out=o4, ctx=ctx))
-            extras[f"batched_{prec}"] = {
-                "workload": "256 clusters, N log-uniform [1024, 32768], active 1-100%",
-                "ms": round(ms, 3), "gpairs_per_s": round(pairs4 / ms * 1e-6, 2),
-                "plan": ctx.last_plan()}
-            log(f"batched {prec}: {ms:.2f} ms, {pairs4 / ms * 1e-6:.1f} G pairs/s")
+            ent = {"workload": "256 clusters, N log-uniform [1024, 32768], active 1-100%",
+                   "default": {"ms": round(ms, 3), "gpairs_per_s": round(pairs4 / ms * 1e-6, 2),
+                               "plan": ctx.last_plan()}}
+            log(f"batched {prec} (default shape): {ms:.2f} ms, "
+                f"{pairs4 / ms * 1e-6:.1f} G pairs/s")
+            c1 = time.perf_counter()
+            nb.autotune_batched(*b4, s4["nb_cap"], prec, out=o4, force=True, ctx=ctx)
+            torch.cuda.synchronize()
+            tune_s = time.perf_counter() - c1
+            ms = steady_ms(
+                lambda: nb.regular_force_batched(*b4, s4["nb_cap"], prec, out=o4, ctx=ctx))
+            ent.update({"ms": round(ms, 3), "gpairs_per_s": round(pairs4 / ms * 1e-6, 2),
+                        "plan": ctx.last_plan(), "tuning_s": round(tune_s, 2)})
+            extras[f"batched_{prec}"] = ent
+            log(f"batched {prec} (tuned, {tune_s:.1f}s to tune): {ms:.2f} ms, "
+                f"{pairs4 / ms * 1e-6:.1f} G pairs/s, {ctx.last_plan()}")
             del o4
 
     if not args.no_levels:
         extras["step"] = step_leg(nb, s, ctx, x, v, a, jk, m, xp, vp, ibd, out, t, t0d)
         extras["sched"] = sched_leg(nb, W, s, ctx, dev)
         extras["radius"] = radius_leg(nb, W, s, ctx, dev, x, v, a, jk, m, precs)
+        extras["small_configs"] = small_configs_leg(nb, W, ctx, dev, precs)
 
-    # CPU oracle on a bounded sample of the same full block
+    # CPU oracle on a bounded sample of the same full block, then the other
+    # workloads in full
     cpu = None
     if args.cpu_rows > 0:
         import oracle
@@ -458,10 +619,10 @@ def main():
         oracle.regular(ox, ov, s["m"], blk[rows], s["rs2"][blk][rows], cap)
         dt = time.perf_counter() - c1
         cpu = {"value": round(rows.size * (n - 1) / dt * 1e-9, 4), "unit": "G pairs/s",
-               "cores": threads, "kind": "oracle",
+               "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{rows.size} random rows of the N=2^20 full block against all "
                          f"{n} bodies ({rows.size * (n - 1):.3g} pairs, {dt:.1f}s, FP64)"}
-        log(f"cpu oracle: {cpu['value']} G pairs/s on {threads} threads")
+        log(f"cpu oracle: {cpu['value']} G pairs/s on {threads} threads ({cpu['cpu_model']})")
         if "sched" in extras:
             # the oracle's plain O(N) search for the next block over all bodies
             import oracle.sched as osched
@@ -472,6 +633,8 @@ def main():
                 osched.next_block(tt, dts)
             extras["sched"]["cpu_oracle_full_search_ms"] = round(
                 (time.perf_counter() - c1) * 1e3 / 5, 3)
+        if not args.no_levels and not args.no_oracle_configs:
+            extras["cpu_oracle_other_workloads"] = oracle_leg(W, threads)
 
     head = res.get("mixed") or res["fp64"]
     dom = "mixed" if "mixed" in res else "fp64"

@@ -229,6 +229,39 @@ int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const int64_t *j_o
                              double *acc, double *jerk, int32_t *nb_count,
                              int32_t *nb_list, int32_t *overflow, uint32_t *status);
 
+/* Batched kernel shape override (tests and the batched tuner): the LDS tile
+ * length (j bodies staged per tile), the work-group width in lanes, the rows
+ * each lane holds, and the work cap (the ensemble's pair work is cut into
+ * items of about 1/(items_per_cu x CUs) of the total, by j-splits of whole
+ * 256-body units).  Built shapes (tile, lanes, rows_per_lane): (256, 256, 1)
+ * (the default), (256, 256, 2), (128, 128, 1), (64, 64, 1), (512, 512, 1),
+ * (256, 512, 1); others give NB_ERR_UNSUPPORTED.  items_per_cu in [1, 4096]
+ * (0 = 64).  All zero = automatic (tuned shape if nb_autotune_batched has
+ * tuned this ensemble, else the default).  Results do not depend on the
+ * shape: a row's sums follow the j order of its cluster's splits, which
+ * depend only on the split count. */
+int nb_ctx_set_batched_shape(nb_ctx *ctx, int tile, int lanes, int rows_per_lane,
+                             int items_per_cu);
+
+/* Autotuner of the batched ensemble (an extension of the regular-force step
+ * of section 3.2.1; the paper runs one cluster at a time): with the same
+ * arguments as nb_regular_force_batched, times every built kernel shape with
+ * work caps of 16, 64 and 256 items per CU (graph replays, best of three)
+ * on the caller's own ensemble, and keeps the fastest for this ensemble
+ * (keyed by precision, nb_cap and both offset arrays); later
+ * nb_regular_force_batched calls on it use that shape.  The outputs are
+ * written by every trial and finally by the tuned shape.  If cache_path
+ * names a file written by an earlier run that holds this ensemble, its
+ * entries are loaded instead (flags & 1 forces re-tuning); after tuning all
+ * tuned ensembles of the context are written there.  Synchronises the
+ * stream.  Errors as nb_regular_force_batched. */
+int nb_autotune_batched(nb_ctx *ctx, int32_t n_clusters, const int64_t *j_off_host,
+                        const int64_t *i_off_host, const double *xp, const double *vp,
+                        const double *m, const int32_t *i_block, const double *rs2,
+                        int32_t nb_cap, nb_precision prec, double *acc, double *jerk,
+                        int32_t *nb_count, int32_t *nb_list, int32_t *overflow,
+                        uint32_t *status, const char *cache_path, int flags);
+
 /* Autotuner: times the candidate plans (rows per lane, splits, mapping) on
  * synthetic Plummer-like data for a ladder of block sizes at the given n,
  * for both precisions, and stores the fastest per (precision, n bucket, n_i

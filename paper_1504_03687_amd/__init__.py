@@ -24,7 +24,8 @@ import torch
 
 __all__ = [
     "NbError", "Context", "lib", "library_path", "context", "predict", "regular_force",
-    "regular_force_adjoint", "regular_force_batched", "autotune", "RegularForce",
+    "regular_force_adjoint", "regular_force_batched", "autotune", "autotune_batched",
+    "regular_force_noalloc", "fixed_workspace_bytes", "RegularForce",
     "irregular_force", "hermite_correct", "potential", "sched_build", "sched_update",
     "sched_next", "radius_update", "regular_force_fit", "FP64", "MIXED", "STATUS_OVERFLOW", "STATUS_BAD_INDEX",
     "STATUS_NONFINITE", "STATUS_BAD_LEVEL",
@@ -93,6 +94,9 @@ def lib() -> C.CDLL:
             "nb_regular_force_batched": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, i32, C.c_int, vp,
                                           vp, vp, vp, vp, u32p], C.c_int),
             "nb_autotune": ([vp, i64, C.c_char_p, C.c_int], C.c_int),
+            "nb_ctx_set_batched_shape": ([vp, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
+            "nb_autotune_batched": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, i32, C.c_int, vp, vp,
+                                     vp, vp, vp, u32p, C.c_char_p, C.c_int], C.c_int),
             "nb_irregular_force": ([vp, i64, vp, vp, vp, i32, vp, i32, vp, vp, vp, vp, u32p],
                                    C.c_int),
             "nb_hermite_correct": ([vp, i64] + [vp] * 11, C.c_int),
@@ -181,6 +185,12 @@ class Context:
 
     def set_plan(self, mapping: int = 0, rows_per_lane: int = 0, splits: int = 0):
         _check(lib().nb_ctx_set_plan(self._h, mapping, rows_per_lane, splits), "nb_ctx_set_plan")
+
+    def set_batched_shape(self, tile: int = 0, lanes: int = 0, rows_per_lane: int = 0,
+                          items_per_cu: int = 0):
+        """Forces the batched kernel shape (all zero: automatic)."""
+        _check(lib().nb_ctx_set_batched_shape(self._h, tile, lanes, rows_per_lane, items_per_cu),
+               "nb_ctx_set_batched_shape")
 
     def last_plan(self) -> str:
         buf = C.create_string_buffer(256)
@@ -352,10 +362,8 @@ def regular_force_adjoint(xp, vp, m, i_block, rs2, w_a, w_j, status=None,
     return gx, gv, gm
 
 
-def regular_force_batched(j_off, i_off, xp, vp, m, i_block, rs2, nb_cap: int,
-                          precision="mixed", status=None, out=None, ctx: Context | None = None):
-    """Batched ensemble (see nbreg.h).  j_off, i_off: host int64 sequences of
-    length n_clusters + 1.  Returns (acc, jerk, nb_count, nb_list, overflow)."""
+def _batched_call(fn: str, j_off, i_off, xp, vp, m, i_block, rs2, nb_cap: int, precision,
+                  status, out, ctx, extra=()):
     import numpy as np
     j_off = np.ascontiguousarray(j_off, dtype=np.int64)
     i_off = np.ascontiguousarray(i_off, dtype=np.int64)
@@ -374,13 +382,30 @@ def regular_force_batched(j_off, i_off, xp, vp, m, i_block, rs2, nb_cap: int,
         _dev(status, "status", torch.int32, (1,))
     ctx = ctx or context(dev.index)
     ctx._bind_stream()
-    _check(lib().nb_regular_force_batched(
+    _check(getattr(lib(), fn)(
         ctx.handle, j_off.size - 1, j_off.ctypes.data_as(C.c_void_p),
         i_off.ctypes.data_as(C.c_void_p), _ptr(xp), _ptr(vp), _ptr(m), _ptr(i_block),
         _ptr(rs2), int(nb_cap), _prec(precision), _ptr(acc), _ptr(jerk), _ptr(cnt),
-        _ptr(lst) if nb_cap > 0 else None, _ptr(ovf), _ptr(status)),
-        "nb_regular_force_batched")
+        _ptr(lst) if nb_cap > 0 else None, _ptr(ovf), _ptr(status), *extra), fn)
     return acc, jerk, cnt, lst, ovf
+
+
+def regular_force_batched(j_off, i_off, xp, vp, m, i_block, rs2, nb_cap: int,
+                          precision="mixed", status=None, out=None, ctx: Context | None = None):
+    """Batched ensemble (see nbreg.h).  j_off, i_off: host int64 sequences of
+    length n_clusters + 1.  Returns (acc, jerk, nb_count, nb_list, overflow)."""
+    return _batched_call("nb_regular_force_batched", j_off, i_off, xp, vp, m, i_block, rs2,
+                         nb_cap, precision, status, out, ctx)
+
+
+def autotune_batched(j_off, i_off, xp, vp, m, i_block, rs2, nb_cap: int, precision="mixed",
+                     status=None, out=None, cache_path: str | None = None, force: bool = False,
+                     ctx: Context | None = None):
+    """Times the batched kernel shapes on this ensemble and keeps the fastest
+    for it (nb_autotune_batched); returns the outputs of the tuned shape."""
+    return _batched_call("nb_autotune_batched", j_off, i_off, xp, vp, m, i_block, rs2, nb_cap,
+                         precision, status, out, ctx,
+                         extra=(cache_path.encode() if cache_path else None, int(bool(force))))
 
 
 def autotune(n: int, cache_path: str | None = None, force: bool = False,

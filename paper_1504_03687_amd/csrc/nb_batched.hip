@@ -14,6 +14,7 @@
 // per shape into a HIP graph and replayed.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -26,10 +27,10 @@
 namespace nb {
 namespace {
 
-template <bool MIXED, int IR>
-__global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A)
+template <bool MIXED, int IR, int T, int NB>
+__global__ __launch_bounds__(NB) void batched_kernel(BatchArgs A)
 {
-    __shared__ JBody tile[2][kTile];
+    __shared__ JBody tile[2][T];
     __shared__ int32_t s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(A.queue, 1);
@@ -43,8 +44,8 @@ __global__ __launch_bounds__(kBlock) void batched_kernel(BatchArgs A)
         const int64_t j1 = j0 + C.split_len < C.j_end ? j0 + C.split_len : C.j_end;
         const Dest d{C.splits == 1, C.slot_base + (int64_t)I.split, (int64_t)C.row_begin,
                      (int64_t)C.splits};
-        rows_pass<MIXED, IR>(A.f, tile, I.row0, (int64_t)C.row_begin + C.n_rows, j0, j1, d,
-                             C.near);
+        rows_pass<MIXED, IR, T, NB>(A.f, tile, I.row0, (int64_t)C.row_begin + C.n_rows, j0, j1,
+                                    d, C.near);
     }
 }
 
@@ -69,41 +70,59 @@ __global__ __launch_bounds__(kBlock) void batched_merge_kernel(BatchArgs A)
     merge_row<W>(A.f, b, has, g);
 }
 
-template <bool MIXED, int IR>
-const void *batched_fn()
+template <bool MIXED, int S>
+const void *batched_fn_t()
 {
-    return (const void *)&batched_kernel<MIXED, IR>;
+    constexpr BShape sh = kBatchedShape[S];
+    return (const void *)&batched_kernel<MIXED, sh.rows_per_lane, sh.tile, sh.lanes>;
+}
+
+template <bool MIXED>
+const void *batched_fn(int shape)
+{
+    static_assert(kBatchedShapes == 6, "one case per shape");
+    switch (shape) {
+    case 0: return batched_fn_t<MIXED, 0>();
+    case 1: return batched_fn_t<MIXED, 1>();
+    case 2: return batched_fn_t<MIXED, 2>();
+    case 3: return batched_fn_t<MIXED, 3>();
+    case 4: return batched_fn_t<MIXED, 4>();
+    case 5: return batched_fn_t<MIXED, 5>();
+    default: return nullptr;
+    }
 }
 
 }  // namespace
 
-int batched_max_blocks_per_cu(bool mixed, int rows_per_lane)
+int batched_shape_index(int tile, int lanes, int rows_per_lane)
 {
-    const void *fn = mixed ? (rows_per_lane == 2 ? batched_fn<true, 2>() : batched_fn<true, 1>())
-                           : (rows_per_lane == 2 ? batched_fn<false, 2>() : batched_fn<false, 1>());
+    for (int k = 0; k < kBatchedShapes; ++k)
+        if (kBatchedShape[k].tile == tile && kBatchedShape[k].lanes == lanes &&
+            kBatchedShape[k].rows_per_lane == rows_per_lane)
+            return k;
+    return -1;
+}
+
+int batched_max_blocks_per_cu(bool mixed, int shape)
+{
+    const void *fn = mixed ? batched_fn<true>(shape) : batched_fn<false>(shape);
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBlock, 0) != hipSuccess) {
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                   &blocks, fn, kBatchedShape[shape].lanes, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
     return blocks > 0 ? blocks : 1;
 }
 
-hipError_t launch_batched(bool mixed, int rows_per_lane, int grid, const BatchArgs &a,
-                          hipStream_t s)
+hipError_t launch_batched(bool mixed, int shape, int grid, const BatchArgs &a, hipStream_t s)
 {
-    if (mixed) {
-        if (rows_per_lane == 2)
-            hipLaunchKernelGGL((batched_kernel<true, 2>), dim3(grid), dim3(kBlock), 0, s, a);
-        else
-            hipLaunchKernelGGL((batched_kernel<true, 1>), dim3(grid), dim3(kBlock), 0, s, a);
-    } else {
-        if (rows_per_lane == 2)
-            hipLaunchKernelGGL((batched_kernel<false, 2>), dim3(grid), dim3(kBlock), 0, s, a);
-        else
-            hipLaunchKernelGGL((batched_kernel<false, 1>), dim3(grid), dim3(kBlock), 0, s, a);
-    }
-    return hipGetLastError();
+    const void *fn = mixed ? batched_fn<true>(shape) : batched_fn<false>(shape);
+    if (!fn) return hipErrorInvalidValue;
+    BatchArgs arg = a;
+    void *args[] = {&arg};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)kBatchedShape[shape].lanes),
+                           args, 0, s);
 }
 
 hipError_t launch_batched_merge(const BatchArgs &a, hipStream_t s)
@@ -132,7 +151,8 @@ struct BatchedCache {
     std::vector<int64_t> j_off, i_off;
     int32_t cap = 0;
     int prec = 0;
-    int rows_per_lane = 1;
+    int shape = 0;            // index into nb::kBatchedShape
+    int items_per_cu = 64;    // work cap: items of ~1/(items_per_cu x CUs) of the pairs
     int forced_splits = 0;
     double redo_k = 0.0;
     const void *ptrs[11] = {};
@@ -172,14 +192,18 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     const int32_t C = (int32_t)c->j_off.size() - 1;
     std::vector<nb::BCluster> cl((size_t)C);
     int64_t slots = 0;
-    // automatic splits: items of at most ~1/(64 per CU) of the total pair
-    // work, so the queue's tail is short (as for single blocks), with
-    // splits of at least 8 tiles
+    // automatic splits: items of at most ~1/(items_per_cu per CU) of the
+    // total pair work, so the queue's tail is short (as for single blocks),
+    // with splits of at least 8 split units
     double total_work = 0.0;
     for (int32_t k = 0; k < C; ++k)
         total_work += (double)(c->i_off[k + 1] - c->i_off[k]) * (double)(c->j_off[k + 1] - c->j_off[k]);
     const double item_work =
-        std::max(1.0, total_work / ((ctx->cu_count > 0 ? ctx->cu_count : 256) * 64.0));
+        std::max(1.0, total_work / ((ctx->cu_count > 0 ? ctx->cu_count : 256) *
+                                    (double)c->items_per_cu));
+    const nb::BShape sh = nb::kBatchedShape[c->shape];
+    const int64_t rows_per_item = (int64_t)sh.rows_per_lane * sh.lanes;
+    constexpr int64_t U = nb::kSplitUnit;
     for (int32_t k = 0; k < C; ++k) {
         const int64_t nc = c->j_off[k + 1] - c->j_off[k];
         const int64_t rc = c->i_off[k + 1] - c->i_off[k];
@@ -187,15 +211,15 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
         if (nc <= 0) {
             S = 1;
         } else if (c->forced_splits > 0) {
-            S = std::min<int64_t>(c->forced_splits, (nc + nb::kTile - 1) / nb::kTile);
+            S = std::min<int64_t>(c->forced_splits, (nc + U - 1) / U);
         } else {
-            const double rows = (double)std::min<int64_t>(rc, (int64_t)c->rows_per_lane * nb::kBlock);
+            const double rows = (double)std::min<int64_t>(rc, rows_per_item);
             S = (int64_t)std::ceil(rows * (double)nc / item_work);
-            S = std::max<int64_t>(1, std::min<int64_t>(S, nc / (8 * nb::kTile)));
+            S = std::max<int64_t>(1, std::min<int64_t>(S, nc / (8 * U)));
         }
-        const int64_t tiles = std::max<int64_t>(1, (nc + nb::kTile - 1) / nb::kTile);
+        const int64_t tiles = std::max<int64_t>(1, (nc + U - 1) / U);
         const int64_t per = (tiles + S - 1) / S;
-        const int64_t split_len = per * nb::kTile;
+        const int64_t split_len = per * U;
         S = nc > 0 ? (nc + split_len - 1) / split_len : 1;
         nb::BCluster &b = cl[(size_t)k];
         b.j_begin = c->j_off[k];
@@ -217,7 +241,6 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
         nb::BItem it;
     };
     std::vector<W> items;
-    const int64_t rows_per_item = (int64_t)c->rows_per_lane * nb::kBlock;
     std::vector<int32_t> merge_rows, row_cluster;
     for (int32_t k = 0; k < C; ++k) {
         const nb::BCluster &b = cl[(size_t)k];
@@ -306,7 +329,7 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     A.max_splits = 1;
     for (int32_t k = 0; k < C; ++k) A.max_splits = std::max(A.max_splits, cl[(size_t)k].splits);
     const int cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
-    c->grid = cus * nb::batched_max_blocks_per_cu(mixed, c->rows_per_lane);
+    c->grid = cus * nb::batched_max_blocks_per_cu(mixed, c->shape);
     if (A.n_items < c->grid) c->grid = std::max(1, A.n_items);
 
     // capture the launch sequence on a private stream (default priority)
@@ -319,7 +342,7 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
         if (le == hipSuccess) le = nb::launch_fill_i32(f.overflow, 0, 1, cs);
         if (le == hipSuccess && c->redo_k > 0.0)
             le = nb::launch_fill_i32(A.f.redo_count, 0, 1, cs);
-        if (le == hipSuccess) le = nb::launch_batched(mixed, c->rows_per_lane, c->grid, A, cs);
+        if (le == hipSuccess) le = nb::launch_batched(mixed, c->shape, c->grid, A, cs);
         if (le == hipSuccess) le = nb::launch_batched_merge(A, cs);
         if (le == hipSuccess && c->redo_k > 0.0)
             le = nb::launch_redo(A.f, cs);
@@ -336,13 +359,37 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
 
 using namespace nbrt;
 
-extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const int64_t *j_off_host,
-                                        const int64_t *i_off_host, const double *xp,
-                                        const double *vp, const double *m,
-                                        const int32_t *i_block, const double *rs2,
-                                        int32_t nb_cap, nb_precision prec, double *acc,
-                                        double *jerk, int32_t *nb_count, int32_t *nb_list,
-                                        int32_t *overflow, uint32_t *status)
+namespace nbrt {
+
+// Key of an ensemble shape for the tuned-shape table: FNV-1a over the
+// precision, list capacity and both offset arrays.
+static uint64_t ensemble_key(int prec, int32_t cap, int32_t C, const int64_t *j_off,
+                             const int64_t *i_off)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)prec);
+    mix((uint64_t)(uint32_t)cap);
+    mix((uint64_t)(uint32_t)C);
+    for (int32_t k = 0; k <= C; ++k) {
+        mix((uint64_t)j_off[k]);
+        mix((uint64_t)i_off[k]);
+    }
+    return h;
+}
+
+// Host-side argument checks shared by the batched call and its tuner.
+static int batched_check(const nb_ctx *ctx, int32_t n_clusters, const int64_t *j_off_host,
+                         const int64_t *i_off_host, const double *xp, const double *vp,
+                         const double *m, const int32_t *i_block, const double *rs2,
+                         int32_t nb_cap, nb_precision prec, const double *acc,
+                         const double *jerk, const int32_t *nb_count, const int32_t *nb_list,
+                         const int32_t *overflow)
 {
     if (!ctx || n_clusters < 1 || !j_off_host || !i_off_host || nb_cap < 0)
         return NB_ERR_INVALID_ARG;
@@ -358,18 +405,51 @@ extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const i
     if (n_rows > 0 && (!i_block || !rs2 || !acc || !jerk || !nb_count)) return NB_ERR_INVALID_ARG;
     if (n_rows > 0 && nb_cap > 0 && !nb_list) return NB_ERR_INVALID_ARG;
     if (!ctx->usable) return NB_ERR_UNSUPPORTED;
+    return NB_OK;
+}
+
+}  // namespace nbrt
+
+extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const int64_t *j_off_host,
+                                        const int64_t *i_off_host, const double *xp,
+                                        const double *vp, const double *m,
+                                        const int32_t *i_block, const double *rs2,
+                                        int32_t nb_cap, nb_precision prec, double *acc,
+                                        double *jerk, int32_t *nb_count, int32_t *nb_list,
+                                        int32_t *overflow, uint32_t *status)
+{
+    int rc = batched_check(ctx, n_clusters, j_off_host, i_off_host, xp, vp, m, i_block, rs2,
+                           nb_cap, prec, acc, jerk, nb_count, nb_list, overflow);
+    if (rc != NB_OK) return rc;
+    const int64_t n = j_off_host[n_clusters];
+    const int64_t n_rows = i_off_host[n_clusters];
 
     const bool mixed = prec == NB_MIXED;
-    const int rpl = (ctx->has_forced && ctx->forced.rows_per_lane == 2) ? 2 : 1;
+    // shape: a forced one, else the tuned one for this ensemble, else the
+    // default (256-body tiles, 256 lanes, one row per lane; two rows per lane
+    // if the single-block plan override asks for them)
+    BatchedChoice ch{(ctx->has_forced && ctx->forced.rows_per_lane == 2) ? 1 : 0, 64};
+    const char *origin = "default";
+    if (ctx->has_batched_forced) {
+        ch = ctx->batched_forced;
+        origin = "forced";
+    } else {
+        auto it = ctx->batched_tuned.find(
+            ensemble_key((int)prec, nb_cap, n_clusters, j_off_host, i_off_host));
+        if (it != ctx->batched_tuned.end()) {
+            ch = it->second;
+            origin = "tuned";
+        }
+    }
     const int fsplits = ctx->has_forced ? ctx->forced.splits : 0;
     const double rk = mixed ? redo_k(ctx) : 0.0;
     const void *ptrs[11] = {xp, vp, m, i_block, rs2, acc, jerk, nb_count, nb_list, overflow,
                             status};
     BatchedCache *hit = nullptr;
     for (auto *c : ctx->batched) {
-        if (c->cap == nb_cap && c->prec == (int)prec && c->rows_per_lane == rpl &&
-            c->forced_splits == fsplits && c->redo_k == rk &&
-            (int32_t)c->j_off.size() == n_clusters + 1 &&
+        if (c->cap == nb_cap && c->prec == (int)prec && c->shape == ch.shape &&
+            c->items_per_cu == ch.items_per_cu && c->forced_splits == fsplits &&
+            c->redo_k == rk && (int32_t)c->j_off.size() == n_clusters + 1 &&
             std::memcmp(c->ptrs, ptrs, sizeof ptrs) == 0 &&
             std::equal(c->j_off.begin(), c->j_off.end(), j_off_host) &&
             std::equal(c->i_off.begin(), c->i_off.end(), i_off_host)) {
@@ -393,7 +473,8 @@ extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const i
         c->i_off.assign(i_off_host, i_off_host + n_clusters + 1);
         c->cap = nb_cap;
         c->prec = (int)prec;
-        c->rows_per_lane = rpl;
+        c->shape = ch.shape;
+        c->items_per_cu = ch.items_per_cu;
         c->forced_splits = fsplits;
         c->redo_k = rk;
         std::memcpy(c->ptrs, ptrs, sizeof ptrs);
@@ -412,7 +493,7 @@ extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const i
         f.nb_list = nb_list;
         f.overflow = overflow;
         f.status = status;
-        int rc = build_cache(ctx, c, f, mixed);
+        rc = build_cache(ctx, c, f, mixed);
         if (rc != NB_OK) {
             release_one(ctx, c);
             return rc;
@@ -422,13 +503,140 @@ extern "C" int nb_regular_force_batched(nb_ctx *ctx, int32_t n_clusters, const i
     }
     hit->last_use = ++g_use_clock;
     ctx->last_redo_counter = hit->redo_k > 0.0 ? hit->args.f.redo_count : nullptr;
+    const nb::BShape &sh = nb::kBatchedShape[hit->shape];
     std::snprintf(ctx->last_plan, sizeof ctx->last_plan,
-                  "batched clusters=%d items=%d grid=%d rows_per_lane=%d merge_rows=%d prec=%s",
-                  n_clusters, hit->args.n_items, hit->grid, hit->rows_per_lane,
-                  hit->args.n_merge_rows, mixed ? "mixed" : "fp64");
+                  "batched clusters=%d items=%d grid=%d tile=%d lanes=%d rows_per_lane=%d "
+                  "items_per_cu=%d merge_rows=%d shape=%s prec=%s",
+                  n_clusters, hit->args.n_items, hit->grid, sh.tile, sh.lanes, sh.rows_per_lane,
+                  hit->items_per_cu, hit->args.n_merge_rows, origin, mixed ? "mixed" : "fp64");
     hipEvent_t ev[2];
     hipError_t e = timed_begin(ctx, NB_CLASS_BATCHED, ev);
     if (e == hipSuccess) e = hipGraphLaunch(hit->exec, ctx->stream);
     if (e == hipSuccess) e = timed_end(ctx, NB_CLASS_BATCHED, ev);
     return e == hipSuccess ? NB_OK : hip_fail(ctx, e);
+}
+
+extern "C" int nb_ctx_set_batched_shape(nb_ctx *ctx, int tile, int lanes, int rows_per_lane,
+                                        int items_per_cu)
+{
+    if (!ctx) return NB_ERR_INVALID_ARG;
+    if (tile == 0 && lanes == 0 && rows_per_lane == 0 && items_per_cu == 0) {
+        ctx->has_batched_forced = false;
+        return NB_OK;
+    }
+    if (items_per_cu < 0 || items_per_cu > 4096) return NB_ERR_INVALID_ARG;
+    const int k = nb::batched_shape_index(tile, lanes, rows_per_lane);
+    if (k < 0) return NB_ERR_UNSUPPORTED;
+    ctx->batched_forced = BatchedChoice{k, items_per_cu > 0 ? items_per_cu : 64};
+    ctx->has_batched_forced = true;
+    return NB_OK;
+}
+
+// Candidate work caps of the batched tuner (items per CU).
+static const int kTuneItemsPerCu[] = {16, 64, 256};
+
+extern "C" int nb_autotune_batched(nb_ctx *ctx, int32_t n_clusters, const int64_t *j_off_host,
+                                   const int64_t *i_off_host, const double *xp, const double *vp,
+                                   const double *m, const int32_t *i_block, const double *rs2,
+                                   int32_t nb_cap, nb_precision prec, double *acc, double *jerk,
+                                   int32_t *nb_count, int32_t *nb_list, int32_t *overflow,
+                                   uint32_t *status, const char *cache_path, int flags)
+{
+    int rc = batched_check(ctx, n_clusters, j_off_host, i_off_host, xp, vp, m, i_block, rs2,
+                           nb_cap, prec, acc, jerk, nb_count, nb_list, overflow);
+    if (rc != NB_OK) return rc;
+    const uint64_t key = ensemble_key((int)prec, nb_cap, n_clusters, j_off_host, i_off_host);
+    if (cache_path && !(flags & 1)) {
+        FILE *f = std::fopen(cache_path, "r");
+        if (f) {
+            char head[64] = {0};
+            bool found = false;
+            if (std::fgets(head, sizeof head, f) &&
+                std::strncmp(head, "nbreg-batched-tune 1", 20) == 0) {
+                unsigned long long kk;
+                int tile, lanes, rows, ipc;
+                while (std::fscanf(f, "%llx %d %d %d %d", &kk, &tile, &lanes, &rows, &ipc) == 5) {
+                    const int sh = nb::batched_shape_index(tile, lanes, rows);
+                    if (sh < 0 || ipc < 1 || ipc > 4096) continue;
+                    ctx->batched_tuned[(uint64_t)kk] = BatchedChoice{sh, ipc};
+                    found |= (uint64_t)kk == key;
+                }
+            }
+            std::fclose(f);
+            if (found) return NB_OK;
+        }
+    }
+    const bool saved_has = ctx->has_batched_forced;
+    const BatchedChoice saved = ctx->batched_forced;
+    const bool saved_timing = ctx->timing;
+    ctx->timing = false;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    float best_ms = 1e30f;
+    BatchedChoice best{0, 64};
+    for (int shape = 0; shape < nb::kBatchedShapes && rc == NB_OK && e == hipSuccess; ++shape)
+        for (int ipc : kTuneItemsPerCu) {
+            ctx->batched_forced = BatchedChoice{shape, ipc};
+            ctx->has_batched_forced = true;
+            // first call builds and captures; then the best of three replays
+            rc = nb_regular_force_batched(ctx, n_clusters, j_off_host, i_off_host, xp, vp, m,
+                                          i_block, rs2, nb_cap, prec, acc, jerk, nb_count,
+                                          nb_list, overflow, status);
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3 && rc == NB_OK && e == hipSuccess; ++rep) {
+                e = hipEventRecord(t0, ctx->stream);
+                if (e != hipSuccess) break;
+                rc = nb_regular_force_batched(ctx, n_clusters, j_off_host, i_off_host, xp, vp,
+                                              m, i_block, rs2, nb_cap, prec, acc, jerk,
+                                              nb_count, nb_list, overflow, status);
+                if (e == hipSuccess) e = hipEventRecord(t1, ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                ms_min = std::min(ms_min, ms);
+            }
+            if (rc != NB_OK || e != hipSuccess) break;
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                best = ctx->batched_forced;
+            }
+            // keep only the cached graph of the best shape so far
+            if (!(best.shape == shape && best.items_per_cu == ipc)) {
+                e = hipStreamSynchronize(ctx->stream);
+                for (auto it = ctx->batched.begin(); it != ctx->batched.end(); ++it)
+                    if ((*it)->shape == shape && (*it)->items_per_cu == ipc &&
+                        (*it)->prec == (int)prec && (*it)->cap == nb_cap) {
+                        release_one(ctx, *it);
+                        ctx->batched.erase(it);
+                        break;
+                    }
+            }
+        }
+    ctx->has_batched_forced = saved_has;
+    ctx->batched_forced = saved;
+    ctx->timing = saved_timing;
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (rc != NB_OK) return rc;
+    if (e != hipSuccess) return hip_fail(ctx, e);
+    ctx->batched_tuned[key] = best;
+    // the caller's outputs end with the tuned shape's results
+    rc = nb_regular_force_batched(ctx, n_clusters, j_off_host, i_off_host, xp, vp, m, i_block,
+                                  rs2, nb_cap, prec, acc, jerk, nb_count, nb_list, overflow,
+                                  status);
+    if (rc != NB_OK) return rc;
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "w");
+        if (f) {
+            std::fprintf(f, "nbreg-batched-tune 1\n");
+            for (auto &kv : ctx->batched_tuned) {
+                const nb::BShape &sh = nb::kBatchedShape[kv.second.shape];
+                std::fprintf(f, "%llx %d %d %d %d\n", (unsigned long long)kv.first, sh.tile,
+                             sh.lanes, sh.rows_per_lane, kv.second.items_per_cu);
+            }
+            std::fclose(f);
+        }
+    }
+    return NB_OK;
 }

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void force_rows_kernel(ForceArgs a)
     const int64_t j0 = (int64_t)split * a.split_len;
     const int64_t j1 = j0 + a.split_len < a.n ? j0 + a.split_len : a.n;
     const Dest d{a.splits == 1, (int64_t)split, 0, (int64_t)a.splits};
-    rows_pass<MIXED, IR>(a, tile, (int64_t)blockIdx.x * IR * kBlock, a.n_i, j0, j1, d,
+    rows_pass<MIXED, IR, kTile, kBlock>(a, tile, (int64_t)blockIdx.x * IR * kBlock, a.n_i, j0, j1, d,
                          a.near_factor);
 }
 

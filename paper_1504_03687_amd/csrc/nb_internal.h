@@ -153,9 +153,24 @@ struct BatchArgs {
     int32_t n_merge_rows;
     int32_t max_splits;          // largest split count of any cluster
 };
-hipError_t launch_batched(bool mixed, int rows_per_lane, int grid, const BatchArgs &a,
-                          hipStream_t s);
+// Shapes the batched kernel is built for: LDS tile length (j bodies per
+// tile), work-group lanes, and rows per lane (a row tile is lanes x rows).
+struct BShape {
+    int tile;
+    int lanes;
+    int rows_per_lane;
+};
+constexpr int kBatchedShapes = 6;
+constexpr BShape kBatchedShape[kBatchedShapes] = {
+    {256, 256, 1}, {256, 256, 2}, {128, 128, 1}, {64, 64, 1}, {512, 512, 1}, {256, 512, 1}};
+// j-splits of the batched ensemble are multiples of this many bodies, for
+// every shape, so a cluster's split boundaries (and so its sums) depend only
+// on its split count.
+constexpr int kSplitUnit = 256;
+// Index of a shape in kBatchedShape, or -1.
+int batched_shape_index(int tile, int lanes, int rows_per_lane);
+hipError_t launch_batched(bool mixed, int shape, int grid, const BatchArgs &a, hipStream_t s);
 hipError_t launch_batched_merge(const BatchArgs &a, hipStream_t s);
-int batched_max_blocks_per_cu(bool mixed, int rows_per_lane);
+int batched_max_blocks_per_cu(bool mixed, int shape);
 
 }  // namespace nb

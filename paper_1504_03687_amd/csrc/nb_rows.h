@@ -262,19 +262,28 @@ __device__ __forceinline__ void flush_flags(const ForceArgs &a, bool ovf, bool b
     }
 }
 
-// Rows [row0 + r*kBlock + tid] (r < IR, < row_end) of one work-group against
-// bodies [j0, j1), staged through the double-buffered LDS tile.  Must be
-// called by the whole work-group (it contains barriers).
-template <bool MIXED, int IR>
-__device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTile],
-                                          int64_t row0, int64_t row_end, int64_t j0,
-                                          int64_t j1, const Dest &d, float near)
+// Rows [row0 + r*NB + tid] (r < IR, < row_end) of one work-group of NB
+// lanes against bodies [j0, j1), staged through a double-buffered LDS tile
+// of T bodies.  With T == NB every lane loads one body of the next tile
+// into registers while the current tile is computed (one barrier per tile);
+// otherwise each lane loads its T/NB bodies (or one, for T < NB) straight
+// into the free buffer when the work-group reaches the tile, so no registers
+// are held across the pair loop.  The j order, the FP32 fold points (every
+// kFold bodies from j0) and all sums are the same for every T and NB, so
+// results do not depend on the tile or work-group shape.  Must be called by
+// the whole work-group (it contains barriers).
+template <bool MIXED, int IR, int T, int NB>
+__device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[T], int64_t row0,
+                                          int64_t row_end, int64_t j0, int64_t j1,
+                                          const Dest &d, float near)
 {
+    static_assert(T % kFold == 0 && NB % kWave == 0, "tile and work-group shape");
+    constexpr bool kPrefetch = T == NB;
     const int tid = threadIdx.x;
     Row<MIXED> R[IR];
 #pragma unroll
     for (int r = 0; r < IR; ++r) {
-        row_init(R[r], a, row0 + r * kBlock + tid, row_end, d, near);
+        row_init(R[r], a, row0 + r * NB + tid, row_end, d, near);
         R[r].jend = (int32_t)j1;
     }
 
@@ -286,19 +295,32 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTil
     for (int r = 0; r < IR; ++r) mine = mine || R[r].i >= 0;
     const bool wave_busy = __ballot(mine) != 0;
 
-    const int64_t ntiles = j1 > j0 ? (j1 - j0 + kTile - 1) / kTile : 0;
+    const int64_t ntiles = j1 > j0 ? (j1 - j0 + T - 1) / T : 0;
     JBody nxt;
-    if (ntiles > 0) {
-        load_body(nxt, a, j0 + tid, j1);
-        tile[0][tid] = nxt;
+    if constexpr (kPrefetch) {
+        if (ntiles > 0) {
+            load_body(nxt, a, j0 + tid, j1);
+            tile[0][tid] = nxt;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int64_t t = 0; t < ntiles; ++t) {
         const int cur = (int)(t & 1);
-        const int64_t tbase = j0 + t * kTile;
-        if (t + 1 < ntiles) load_body(nxt, a, tbase + kTile + tid, j1);
+        const int64_t tbase = j0 + t * T;
+        if constexpr (kPrefetch) {
+            if (t + 1 < ntiles) load_body(nxt, a, tbase + T + tid, j1);
+        } else {
+            // buffer cur was last read for tile t-2, and every wave has
+            // passed the barrier of tile t-1 since
+            for (int k = tid; k < T; k += NB) {
+                JBody J;
+                load_body(J, a, tbase + k, j1);
+                tile[cur][k] = J;
+            }
+            __syncthreads();
+        }
         const JBody *buf = tile[cur];
-        for (int jj = 0; jj < (wave_busy ? kTile : 0); jj += kFold) {
+        for (int jj = 0; jj < (wave_busy ? T : 0); jj += kFold) {
             for (int q = 0; q < kFold; q += 2) {
                 const int32_t jidx = (int32_t)(tbase + jj + q);
 #pragma unroll
@@ -310,15 +332,18 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[kTil
                 for (int r = 0; r < IR; ++r) R[r].S.fold();
             }
         }
-        if (t + 1 < ntiles) tile[cur ^ 1][tid] = nxt;
-        __syncthreads();
+        if constexpr (kPrefetch) {
+            if (t + 1 < ntiles) tile[cur ^ 1][tid] = nxt;
+            __syncthreads();
+        }
     }
+    if constexpr (!kPrefetch) __syncthreads();   // the tile may be reused by the caller
 
     bool ovf = false, bad = false, nonfin = false;
 #pragma unroll
     for (int r = 0; r < IR; ++r) {
         if constexpr (!MIXED) R[r].S.fold();
-        const int64_t b = row0 + r * kBlock + tid;
+        const int64_t b = row0 + r * NB + tid;
         if (b < row_end) {
             bool o = false, bd = false, f = false;
             row_store<MIXED>(a, b, d, R[r].i >= 0, R[r].S, R[r].cnt, o, bd, f, j0, j1);

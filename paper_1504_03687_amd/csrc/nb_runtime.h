@@ -26,6 +26,12 @@ enum {
 };
 
 namespace nbrt {
+// Batched ensemble: a kernel shape (index into nb::kBatchedShape) and the
+// work cap (items per CU).
+struct BatchedChoice {
+    int shape;
+    int items_per_cu;
+};
 struct PendingTiming {
     int cls;
     hipEvent_t start, stop;
@@ -72,6 +78,10 @@ struct nb_ctx {
     int32_t *last_redo_counter = nullptr;   // device counter of the last mixed call
     // batched entry point: cached device metadata and graphs per shape
     std::vector<nbrt::BatchedCache *> batched;
+    // batched kernel shape: forced (tests, the tuner) or tuned per ensemble
+    bool has_batched_forced = false;
+    nbrt::BatchedChoice batched_forced{0, 64};
+    std::map<uint64_t, nbrt::BatchedChoice> batched_tuned;
 };
 
 namespace nbrt {

@@ -157,3 +157,103 @@ def test_cluster_ensemble_256(ctx):
                                        ctx=ctx)
         w = _check(E, out, s["nb_cap"], TOL[prec], rows_per_cluster=12)
         say(f"  {prec}: {ctx.last_plan()}  worst err {w:.2e}")
+
+
+SHAPES = [(256, 256, 1), (256, 256, 2), (128, 128, 1), (64, 64, 1), (512, 512, 1), (256, 512, 1)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_shapes_equal_single_launches(ctx, prec):
+    """Every built kernel shape of the batched ensemble (LDS tile length,
+    work-group width, rows per lane) and work cap gives rows bit-identical to
+    single-block launches with the same split count on each cluster alone."""
+    E = _ensemble(seed=13)
+    args = (E["j_off"], E["i_off"], dev(E["x"]), dev(E["v"]), dev(E["m"]), dev(E["ib"]),
+            dev(E["rs2"]))
+    try:
+        for splits in (1, 3):
+            ctx.set_batched_shape()
+            ctx.set_plan(1, 1, splits)
+            singles = []
+            for c in range(len(E["j_off"]) - 1):
+                j0, j1 = E["j_off"][c], E["j_off"][c + 1]
+                r0, r1 = E["i_off"][c], E["i_off"][c + 1]
+                if r1 == r0:
+                    singles.append(None)
+                    continue
+                singles.append([host(t) for t in nb.regular_force(
+                    dev(E["x"][:, j0:j1]), dev(E["v"][:, j0:j1]), dev(E["m"][j0:j1]),
+                    dev((E["ib"][r0:r1] - j0).astype(np.int32)), dev(E["rs2"][r0:r1]), 32,
+                    prec, ctx=ctx)])
+            for shape in SHAPES:
+                for ipc in (16, 256):
+                    ctx.set_batched_shape(*shape, ipc)
+                    out = [host(t) for t in nb.regular_force_batched(*args, 32, prec, ctx=ctx)]
+                    plan = ctx.last_plan()
+                    say(f"  {prec} splits={splits}: {plan}")
+                    assert f"tile={shape[0]} lanes={shape[1]} rows_per_lane={shape[2]}" in plan
+                    assert f"items_per_cu={ipc}" in plan and "shape=forced" in plan
+                    for c, single in enumerate(singles):
+                        if single is None:
+                            continue
+                        j0 = E["j_off"][c]
+                        r0, r1 = E["i_off"][c], E["i_off"][c + 1]
+                        assert np.array_equal(out[0][:, r0:r1], single[0]), (shape, c)
+                        assert np.array_equal(out[1][:, r0:r1], single[1]), (shape, c)
+                        assert np.array_equal(out[2][r0:r1], single[2]), (shape, c)
+                        for b in range(r1 - r0):
+                            k = min(int(single[2][b]), 32)
+                            assert np.array_equal(out[3][r0 + b, :k], single[3][b, :k] + j0)
+    finally:
+        ctx.set_batched_shape()
+        ctx.set_plan(0, 0, 0)
+
+
+def test_batched_shape_override_rejects_unbuilt_shapes(ctx):
+    with pytest.raises(nb.NbError) as err:
+        ctx.set_batched_shape(192, 256, 1, 64)
+    assert err.value.code == -4
+    with pytest.raises(nb.NbError) as err:
+        ctx.set_batched_shape(256, 256, 1, 5000)
+    assert err.value.code == -1
+    ctx.set_batched_shape()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_batched_autotune(tmp_path, prec):
+    """The batched tuner picks a shape for this ensemble; its outputs match
+    the oracle, later calls use the tuned shape with the same bits, and a
+    fresh context loads the choice from the cache file without re-timing."""
+    E = _ensemble(seed=17)
+    args = (E["j_off"], E["i_off"], dev(E["x"]), dev(E["v"]), dev(E["m"]), dev(E["ib"]),
+            dev(E["rs2"]))
+    path = str(tmp_path / "batched.txt")
+    c1 = nb.Context(0)
+    try:
+        tuned = nb.autotune_batched(*args, 24, prec, cache_path=path, force=True, ctx=c1)
+        plan = c1.last_plan()
+        say(f"  tuned {prec}: {plan}")
+        assert "shape=tuned" in plan
+        _check(E, tuned, 24, TOL[prec])
+        first = [host(t).copy() for t in tuned]
+
+        def same(out):
+            got = [host(t) for t in out]
+            for k in (0, 1, 2, 4):
+                assert np.array_equal(first[k], got[k])
+            check_lists(got[2], got[3], first[2], first[3], 24)   # defined entries only
+
+        same(nb.regular_force_batched(*args, 24, prec, ctx=c1))
+        assert c1.last_plan() == plan
+        with open(path) as f:
+            lines = f.read().splitlines()
+        assert lines[0] == "nbreg-batched-tune 1" and len(lines) == 2
+        c2 = nb.Context(0)
+        try:
+            nb.autotune_batched(*args, 24, prec, cache_path=path, ctx=c2)
+            same(nb.regular_force_batched(*args, 24, prec, ctx=c2))
+            assert c2.last_plan() == plan
+        finally:
+            c2.close()
+    finally:
+        c1.close()
