@@ -132,6 +132,30 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def small_blocks_leg(nb, ctx, dev, s, xp, vp, m, cap, precs):
+    """Blocks of 1, 32 and 1024 random rows of the 2^20 cluster (HBM- and
+    launch-bound), in steady state with outputs reused across calls, as in a
+    stepping loop."""
+    n = s["n"]
+    small = {}
+    rng = np.random.default_rng(1)
+    for size in (1, 32, 1024):
+        sb = rng.choice(n, size, replace=False).astype(np.int32)
+        bd, rd = dev(sb), dev(s["rs2"][sb])
+        ent = {}
+        for prec in precs:
+            o = nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
+            us = 1e3 * steady_ms(
+                lambda: nb.regular_force(xp, vp, m, bd, rd, cap, prec, out=o, ctx=ctx))
+            ent[prec] = {"us": round(us, 1),
+                         "gpairs_per_s": round(size * (n - 1) / us * 1e-3, 2),
+                         "jset_GB_per_s": round(56.0 * n / us * 1e-3, 1),
+                         "plan": ctx.last_plan()}
+        small[str(size)] = ent
+        log(f"small block n_i={size}: " + " ".join(f"{pp}={ent[pp]['us']} us" for pp in precs))
+    return small
+
+
 def adjoint_leg(nb, W, ctx, dev):
     """Adjoint of the regular force at N = 65536 Plummer + Kroupa, all bodies
     active, FP64, in steady state; roofline by the algorithmic flops of both
@@ -415,6 +439,9 @@ def main():
     ap.add_argument("--sched-only", action="store_true",
                     help="only time the block-step scheduler on the same cluster's levels "
                          "and print its figures (used for kernel profiles)")
+    ap.add_argument("--small-only", action="store_true",
+                    help="only time the small blocks (1, 32, 1024 random rows of the 2^20 "
+                         "cluster) and print their figures (used for kernel profiles)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only time the adjoint at N = 65536 (all active, FP64) and print "
                          "its figures (used for kernel profiles)")
@@ -479,6 +506,12 @@ def main():
         return
     if args.sched_only:
         print(json.dumps({"sched": sched_leg(nb, W, s, ctx, dev)}), flush=True)
+        return
+    if args.small_only:
+        nb.predict(x, v, a, jk, t0d, t, out=(xp, vp), ctx=ctx)
+        precs = ["mixed", "fp64"] if args.only == "both" else [args.only]
+        print(json.dumps({"small_blocks": small_blocks_leg(nb, ctx, dev, s, xp, vp, m, cap,
+                                                           precs)}), flush=True)
         return
 
     def step(prec):
@@ -545,23 +578,7 @@ def main():
     # small blocks (HBM / latency bound): random rows of the same cluster
     small = {}
     if not args.no_levels:
-        rng = np.random.default_rng(1)
-        for size in (1, 32, 1024):
-            sb = rng.choice(n, size, replace=False).astype(np.int32)
-            bd, rd = dev(sb), dev(s["rs2"][sb])
-            ent = {}
-            for prec in precs:
-                # outputs reused across calls, as in a stepping loop
-                o = nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
-                us = 1e3 * steady_ms(
-                    lambda: nb.regular_force(xp, vp, m, bd, rd, cap, prec, out=o, ctx=ctx))
-                ent[prec] = {"us": round(us, 1),
-                             "gpairs_per_s": round(size * (n - 1) / us * 1e-3, 2),
-                             "jset_GB_per_s": round(56.0 * n / us * 1e-3, 1),
-                             "plan": ctx.last_plan()}
-            small[str(size)] = ent
-            log(f"small block n_i={size}: " + " ".join(
-                f"{pp}={ent[pp]['us']} us" for pp in precs))
+        small = small_blocks_leg(nb, ctx, dev, s, xp, vp, m, cap, precs)
 
     # adjoint (N = 65536 all active, FP64) and the batched ensemble
     # (256 clusters, one graph launch), each timed in steady state

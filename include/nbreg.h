@@ -20,6 +20,11 @@
  *  - Every call is asynchronous on the context's stream and returns before
  *    the GPU work finishes; read outputs after synchronising that stream.
  *    Growing the context's scratch memory may synchronise the device.
+ *    Calls on one context must not overlap in time: the context keeps device
+ *    words of its own (the mixed-precision refinement counter) that each
+ *    regular-force call uses.  Calls queued on the context's one stream are
+ *    ordered; after nb_ctx_set_stream, order the new stream after the old
+ *    one's pending work.
  *  - Return value: NB_OK (0) or a negative NB_ERR_* code.  Host-checkable
  *    argument errors are reported this way and launch nothing.  Nothing throws
  *    across the ABI.

@@ -130,17 +130,19 @@ __global__ __launch_bounds__(kBlock) void adj_rows_kernel(AdjointArgs a, AdjPlan
     // the factor -3 is applied once per row.
     double C1 = 0, C2 = 0, Hx = 0, Hy = 0, Hz = 0, Ux = 0, Uy = 0, Uz = 0;
 
+    // Each tile is loaded when the work-group reaches it, into the buffer
+    // last read for tile t-2 (every wave has passed tile t-1's barrier since):
+    // one barrier per tile and no registers held across the pair loop.
     const int64_t ntiles = j1 > j0 ? (j1 - j0 + kTile - 1) / kTile : 0;
-    JB nxt;
-    if (ntiles > 0) {
-        load_jb(nxt, a, j0 + tid, j1);
-        tile[0][tid] = nxt;
-    }
-    __syncthreads();
     for (int64_t t = 0; t < ntiles; ++t) {
         const int cur = (int)(t & 1);
         const int64_t tbase = j0 + t * kTile;
-        if (t + 1 < ntiles) load_jb(nxt, a, tbase + kTile + tid, j1);
+        {
+            JB J;
+            load_jb(J, a, tbase + tid, j1);
+            tile[cur][tid] = J;
+        }
+        __syncthreads();
         const JB *buf = tile[cur];
 #pragma unroll 2
         for (int jj = 0; jj < kTile; ++jj) {
@@ -170,8 +172,6 @@ __global__ __launch_bounds__(kBlock) void adj_rows_kernel(AdjointArgs a, AdjPlan
             Uy = __builtin_fma(tb, dy, Uy);
             Uz = __builtin_fma(tb, dz, Uz);
         }
-        if (t + 1 < ntiles) tile[cur ^ 1][tid] = nxt;
-        __syncthreads();
     }
     if (b < a.n_i) {
         double *o = p.row_partial + (int64_t)split * 6 * a.n_i + b;
@@ -260,19 +260,20 @@ __global__ __launch_bounds__(kBlock) void adj_bodies_kernel(AdjointArgs a, AdjPl
     double UAx = 0, UAy = 0, UAz = 0, UBx = 0, UBy = 0, UBz = 0, MA = 0, MB = 0;
     double Dx = 0, Dy = 0, Dz = 0, Dux = 0, Duy = 0, Duz = 0;
 
+    // row tiles are loaded as in the row pass: when reached, into the buffer
+    // last read two tiles ago, one barrier per tile
     const int64_t ntiles = b1 > b0 ? (b1 - b0 + kRowTile - 1) / kRowTile : 0;
-    RB nxt;
-    if (ntiles > 0 && tid < kRowTile) {
-        load_rb(nxt, a, b0 + tid, b1);
-        tile[0][tid] = nxt;
-    }
-    __syncthreads();
     for (int64_t t = 0; t < ntiles; ++t) {
         const int cur = (int)(t & 1);
         const int64_t tbase = b0 + t * kRowTile;
-        if (t + 1 < ntiles && tid < kRowTile) load_rb(nxt, a, tbase + kRowTile + tid, b1);
+        if (tid < kRowTile) {
+            RB R;
+            load_rb(R, a, tbase + tid, b1);
+            tile[cur][tid] = R;
+        }
+        __syncthreads();
         const RB *buf = tile[cur];
-#pragma unroll 2
+#pragma unroll 1
         for (int q = 0; q < kRowTile; ++q) {
             const RB &R = buf[q];
             const double dx = xj - R.x, dy = yj - R.y, dz = zj - R.z;
@@ -319,8 +320,6 @@ __global__ __launch_bounds__(kBlock) void adj_bodies_kernel(AdjointArgs a, AdjPl
                 Duz += rp[5 * (int64_t)a.n_i];
             }
         }
-        if (t + 1 < ntiles && tid < kRowTile) tile[cur ^ 1][tid] = nxt;
-        __syncthreads();
     }
     if (live) {
         double *o = p.body_partial + (int64_t)split * 7 * a.n + j;

@@ -44,28 +44,40 @@ __device__ __forceinline__ double rsqrt_f64(double r2)
 template <bool MIXED>
 struct Sums;
 
-// FP64: the jerk is kept as two sums, sum m r^-3 u (jx..jz) and
-// sum m (r.u) r^-5 r (rx..rz), combined once by fold() as jx - 3 rx, so the
-// factor -3 is not multiplied in for every pair.  fold() must run before the
-// sums are read; it is idempotent.
+// FP64: pair terms go into partial sums over runs of j, which fold() adds
+// into the running sums (ax..jz).  Summing a long j-range in runs keeps the
+// rounding of the running sums from growing with the whole range: a row of
+// 2^18 terms sums 2^10 runs of 2^8 instead of 2^18 single terms, so its
+// error stays far below 1e-12 even where the jerk cancels strongly.  The
+// jerk partial is kept as two parts, sum m r^-3 u (pjx..) and
+// sum m (r.u) r^-5 r (prx..), combined at the fold as pj - 3 pr, so the
+// factor -3 is not multiplied in for every pair.  fold() must run before
+// the sums are read; it is idempotent.
 template <>
 struct Sums<false> {
     double ax, ay, az, jx, jy, jz;
     double va, vj;   // unused in FP64 (kept for a common slot layout)
-    double rx, ry, rz;
+    double pax, pay, paz, pjx, pjy, pjz, prx, pry, prz;
     __device__ __forceinline__ void zero()
     {
         ax = ay = az = jx = jy = jz = va = vj = 0.0;
-        rx = ry = rz = 0.0;
+        pax = pay = paz = pjx = pjy = pjz = prx = pry = prz = 0.0;
     }
     __device__ __forceinline__ void fold()
     {
-        jx = __builtin_fma(-3.0, rx, jx);
-        jy = __builtin_fma(-3.0, ry, jy);
-        jz = __builtin_fma(-3.0, rz, jz);
-        rx = ry = rz = 0.0;
+        ax += pax;
+        ay += pay;
+        az += paz;
+        jx += __builtin_fma(-3.0, prx, pjx);
+        jy += __builtin_fma(-3.0, pry, pjy);
+        jz += __builtin_fma(-3.0, prz, pjz);
+        pax = pay = paz = pjx = pjy = pjz = prx = pry = prz = 0.0;
     }
 };
+
+// The FP64 row kernels fold their partial sums every kFoldF64 bodies from
+// the start of the j-range (at the same positions for every tile length).
+constexpr int kFoldF64 = 256;
 
 // va, vj: sums of the squared norms of the folded FP32 partials.  For terms of
 // varying sign this estimates sum |term|^2, the scale of the accumulated FP32
@@ -119,15 +131,15 @@ __device__ __forceinline__ void accum_f64(Sums<false> &S, double dx, double dy, 
     const double mr3 = (mj * y) * y2;               // m / r^3
     const double s = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
     const double q = (s * y2) * mr3;                // m (r.u) / r^5; -3 applied by fold()
-    S.ax = __builtin_fma(mr3, dx, S.ax);
-    S.ay = __builtin_fma(mr3, dy, S.ay);
-    S.az = __builtin_fma(mr3, dz, S.az);
-    S.jx = __builtin_fma(mr3, ux, S.jx);
-    S.jy = __builtin_fma(mr3, uy, S.jy);
-    S.jz = __builtin_fma(mr3, uz, S.jz);
-    S.rx = __builtin_fma(q, dx, S.rx);
-    S.ry = __builtin_fma(q, dy, S.ry);
-    S.rz = __builtin_fma(q, dz, S.rz);
+    S.pax = __builtin_fma(mr3, dx, S.pax);
+    S.pay = __builtin_fma(mr3, dy, S.pay);
+    S.paz = __builtin_fma(mr3, dz, S.paz);
+    S.pjx = __builtin_fma(mr3, ux, S.pjx);
+    S.pjy = __builtin_fma(mr3, uy, S.pjy);
+    S.pjz = __builtin_fma(mr3, uz, S.pjz);
+    S.prx = __builtin_fma(q, dx, S.prx);
+    S.pry = __builtin_fma(q, dy, S.pry);
+    S.prz = __builtin_fma(q, dz, S.prz);
 }
 
 // Mixed regular term: FP32 arithmetic on the FP32-rounded FP64 differences.

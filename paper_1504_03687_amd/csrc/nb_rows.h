@@ -161,12 +161,16 @@ __device__ __forceinline__ void pair_rows2(Row<MIXED> &R, const JBody &J0, const
         const float r0 = __builtin_fmaf(fz0, fz0, __builtin_fmaf(fy0, fy0, fx0 * fx0));
         const float r1 = __builtin_fmaf(fz1, fz1, __builtin_fmaf(fy1, fy1, fx1 * fx1));
         const bool c0 = r0 < R.candf, c1 = r1 < R.candf;
+        // the FP32 terms first, the rare cases after them: every LDS read of
+        // the two bodies can then be issued before the first arithmetic (the
+        // rare cases touch only the FP64 sums and the list, so the order of
+        // the two changes no result)
+        accum_mixed(R.S, fx0, fy0, fz0, r0, J0.vx - R.vx, J0.vy - R.vy, J0.vz - R.vz, J0.m32, c0);
+        accum_mixed(R.S, fx1, fy1, fz1, r1, J1.vx - R.vx, J1.vy - R.vy, J1.vz - R.vz, J1.m32, c1);
         if (c0 || c1) {
             if (c0) rare_mixed<MIXED>(R, J0, jidx0, r0, dx0, dy0, dz0);
             if (c1) rare_mixed<MIXED>(R, J1, jidx0 + 1, r1, dx1, dy1, dz1);
         }
-        accum_mixed(R.S, fx0, fy0, fz0, r0, J0.vx - R.vx, J0.vy - R.vy, J0.vz - R.vz, J0.m32, c0);
-        accum_mixed(R.S, fx1, fy1, fz1, r1, J1.vx - R.vx, J1.vy - R.vy, J1.vz - R.vz, J1.m32, c1);
     } else {
         const double dx0 = J0.x - R.x, dy0 = J0.y - R.y, dz0 = J0.z - R.z;
         const double dx1 = J1.x - R.x, dy1 = J1.y - R.y, dz1 = J1.z - R.z;
@@ -328,6 +332,9 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[T], 
                     pair_rows2<MIXED>(R[r], buf[jj + q], buf[jj + q + 1], jidx);
             }
             if constexpr (MIXED) {
+#pragma unroll
+                for (int r = 0; r < IR; ++r) R[r].S.fold();
+            } else if (((t * T + jj + kFold) & (kFoldF64 - 1)) == 0) {
 #pragma unroll
                 for (int r = 0; r < IR; ++r) R[r].S.fold();
             }

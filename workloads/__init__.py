@@ -16,7 +16,9 @@ Every array is float64 SoA: positions ``x`` have shape ``(3, n)``.
 from __future__ import annotations
 
 import functools
+import json
 import math
+import os
 
 import numpy as np
 from scipy.spatial import cKDTree
@@ -24,8 +26,30 @@ from scipy.spatial import cKDTree
 SEED_BASE = 1504036870
 
 #: Henon units: G = M = 1, E = -1/4.  A Plummer sphere of scale length b has
-#: E = -3 pi / (64 b) at G = M = 1, so E = -1/4 needs b = 3 pi / 16.
+#: E = -3 pi / (64 b) at G = M = 1, so E = -1/4 needs b = 3 pi / 16.  Samples
+#: are drawn at this scale; the named workloads below are then rescaled
+#: exactly (see henon_correction).
 PLUMMER_B = 3.0 * math.pi / 16.0
+
+_HENON_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "henon_scale.json")
+
+
+@functools.lru_cache(maxsize=1)
+def _henon_table() -> dict:
+    with open(_HENON_TABLE) as f:
+        return json.load(f)
+
+
+def henon_correction(key: str):
+    """(cx, cv): the factors that take the sampled (analytically scaled) state
+    of a named workload to exact Henon units.  With U the potential energy and
+    T the kinetic energy of the sampled state (total mass 1), x -> cx x and
+    v -> cv v with cx = -2 U and cv = 1 / (2 sqrt(T)) give U = -1/2 and
+    T = 1/4, so E = -1/4 and 2T = -U.  The factors are computed once, with the
+    oracle's O(N^2) potential, by workloads/henon_scale.py and stored in
+    henon_scale.json."""
+    e = _henon_table()[key]
+    return float(e["cx"]), float(e["cv"])
 
 
 def rng_for(k: int, *spawn) -> np.random.Generator:
@@ -102,8 +126,10 @@ def _centre(x, v, m):
     v -= (v @ m)[:, None] / m.sum()
 
 
-def plummer(rng: np.random.Generator, n: int, imf: str = "equal"):
-    """Plummer sphere of ``n`` bodies, total mass 1, centre of mass at rest at 0."""
+def plummer(rng: np.random.Generator, n: int, imf: str = "equal", henon_key: str | None = None):
+    """Plummer sphere of ``n`` bodies, total mass 1, centre of mass at rest at 0.
+    With ``henon_key`` the state is rescaled to exact Henon units by the stored
+    factors of that workload (henon_correction)."""
     x, v = plummer_positions_velocities(rng, n)
     if imf == "equal":
         m = np.full(n, 1.0 / n)
@@ -113,6 +139,10 @@ def plummer(rng: np.random.Generator, n: int, imf: str = "equal"):
     else:
         raise ValueError(imf)
     _centre(x, v, m)
+    if henon_key is not None:
+        cx, cv = henon_correction(henon_key)
+        x *= cx
+        v *= cv
     return np.ascontiguousarray(x), np.ascontiguousarray(v), m
 
 
@@ -128,7 +158,8 @@ def _kepler_E(M, e, iters=40):
 
 
 def plummer_with_binaries(rng: np.random.Generator, n: int, n_bin: int,
-                          a_lo=1e-5, a_hi=1e-3):
+                          a_lo=1e-5, a_hi=1e-3, henon_key: str | None = None,
+                          cm_only: bool = False):
     """``n`` bodies of which ``2*n_bin`` are components of primordial binaries.
 
     Centres of mass (n - n_bin of them) follow a Plummer sphere; every component
@@ -136,7 +167,11 @@ def plummer_with_binaries(rng: np.random.Generator, n: int, n_bin: int,
     axis log-uniform in [a_lo, a_hi], thermal eccentricity (e = sqrt(U)),
     isotropic orientation, uniform mean anomaly.  Binary components occupy
     indices 0 .. 2*n_bin-1, pairs adjacent (2k, 2k+1).
-    Returns x, v, m and the per-body orbital period (0 for single stars).
+    With ``henon_key`` the centre-of-mass system is rescaled to exact Henon
+    units (henon_correction) before the binary orbits are added.
+    Returns x, v, m and the per-body orbital period (0 for single stars); with
+    ``cm_only`` the centre-of-mass system (xc, vc, mc) right before that
+    rescaling instead.
     """
     n_cm = n - n_bin
     xc, vc = plummer_positions_velocities(rng, n_cm)
@@ -147,6 +182,12 @@ def plummer_with_binaries(rng: np.random.Generator, n: int, n_bin: int,
     m1, m2, ms = m1 / tot, m2 / tot, ms / tot
     mc = np.concatenate([m1 + m2, ms])
     _centre(xc, vc, mc)
+    if cm_only:
+        return xc, vc, mc
+    if henon_key is not None:
+        cx, cv = henon_correction(henon_key)
+        xc *= cx
+        vc *= cv
 
     a = np.exp(rng.uniform(math.log(a_lo), math.log(a_hi), n_bin))
     e = np.sqrt(rng.random(n_bin))
@@ -308,10 +349,11 @@ def _state(x, v, m, a, jk, t0, t, rs2):
                 t0=t0, t=float(t), rs2=rs2, n=int(m.size))
 
 
-def uniform_step_state(rng, n, imf, dt_k=8, k_nn=64):
+def uniform_step_state(rng, n, imf, dt_k=8, k_nn=64, henon_key: str | None = None):
     """Plummer state where every body has step 2^-dt_k, t0 = 0, t = 2^-dt_k."""
-    x, v, m = plummer(rng, n, imf)
-    a, jk = plummer_field(x, v)
+    x, v, m = plummer(rng, n, imf, henon_key)
+    b = PLUMMER_B * (henon_correction(henon_key)[0] if henon_key is not None else 1.0)
+    a, jk = plummer_field(x, v, b)
     rs2 = knn_rs2(x, k_nn) if n > k_nn else np.full(n, 0.0)
     t = 2.0 ** -dt_k
     return _state(x, v, m, a, jk, np.zeros(n), t, rs2)
@@ -320,7 +362,7 @@ def uniform_step_state(rng, n, imf, dt_k=8, k_nn=64):
 @functools.lru_cache(maxsize=4)
 def plummer_equal_n1024():
     """N = 1024 equal-mass Plummer, all active, nb_cap 256, FP64."""
-    s = uniform_step_state(rng_for(1), 1024, "equal")
+    s = uniform_step_state(rng_for(1), 1024, "equal", henon_key="plummer_equal_n1024")
     s["i_block"] = np.arange(1024, dtype=np.int32)
     s["nb_cap"] = 256
     return s
@@ -330,7 +372,8 @@ def plummer_equal_n1024():
 def plummer_kroupa_n131072(n: int = 131072):
     """N = 131072 Plummer + Kroupa; random blocks of 1, 32, 1024, 16384, N."""
     rng = rng_for(2)
-    s = uniform_step_state(rng, n, "kroupa")
+    s = uniform_step_state(rng, n, "kroupa",
+                           henon_key="plummer_kroupa_n131072" if n == 131072 else None)
     sizes = [sz for sz in (1, 32, 1024, 16384, n) if sz <= n]
     s["blocks"] = {sz: random_block(rng, n, sz) for sz in sizes}
     s["nb_cap"] = 512
@@ -343,9 +386,10 @@ def binary_cluster_n1m(n: int = 1 << 20):
     binaries); Hermite step levels 3..20; nb_cap 1024."""
     rng = rng_for(3)
     n_bin = n // 40
-    x, v, m, period = plummer_with_binaries(rng, n, n_bin)
+    key = "binary_cluster_n1m" if n == 1 << 20 else None
+    x, v, m, period = plummer_with_binaries(rng, n, n_bin, henon_key=key)
     rs2 = knn_rs2(x, 64)
-    a, jk = plummer_field(x, v)
+    a, jk = plummer_field(x, v, PLUMMER_B * (henon_correction(key)[0] if key else 1.0))
     ab, jb = binary_companion_field(x, v, m, n_bin)
     a += ab
     jk += jb
@@ -377,7 +421,8 @@ def cluster_ensemble_256(n_clusters: int = 256, n_lo: int = 1024, n_hi: int = 32
     for c in range(n_clusters):
         rc = rng_for(4, c)
         nc = int(ns[c])
-        st = uniform_step_state(rc, nc, "kroupa")
+        key = f"cluster_ensemble_256/{c}" if (n_clusters, n_lo, n_hi) == (256, 1024, 32768) else None
+        st = uniform_step_state(rc, nc, "kroupa", henon_key=key)
         ni = max(1, int(round(fr[c] * nc)))
         blk = random_block(rc, nc, ni) + j_off[-1]
         xs.append(st["x"]); vs.append(st["v"]); ms.append(st["m"])
@@ -401,7 +446,8 @@ def cluster_ensemble_256(n_clusters: int = 256, n_lo: int = 1024, n_hi: int = 32
 def adjoint_plummer_n65536(n: int = 65536):
     """N = 65536 Plummer + Kroupa, all active; random upstream weights."""
     rng = rng_for(5)
-    s = uniform_step_state(rng, n, "kroupa")
+    s = uniform_step_state(rng, n, "kroupa",
+                           henon_key="adjoint_plummer_n65536" if n == 65536 else None)
     s["i_block"] = np.arange(n, dtype=np.int32)
     s["w_a"] = rng.standard_normal((3, n))
     s["w_j"] = rng.standard_normal((3, n))
