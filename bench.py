@@ -112,6 +112,26 @@ def steady_ms(call, warm_ms=30.0, time_ms=50.0, min_reps=3):
     return (time.perf_counter() - c1) * 1e3 / reps
 
 
+def graph_ms(call, per_graph=10):
+    """Mean time of one call replayed from a captured graph of per_graph
+    back-to-back calls: the GPU time of the call's launch chain without the
+    host's per-call work (argument checks, plan lookup, launches)."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        call()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, capture_error_mode="thread_local"):
+        for _ in range(per_graph):
+            call()
+    ms = steady_ms(g.replay) / per_graph
+    del g
+    return ms
+
+
 def cpu_model() -> str:
     """Host CPU model name (lscpu, else /proc/cpuinfo)."""
     import subprocess
@@ -135,7 +155,8 @@ def cpu_model() -> str:
 def small_blocks_leg(nb, ctx, dev, s, xp, vp, m, cap, precs):
     """Blocks of 1, 32 and 1024 random rows of the 2^20 cluster (HBM- and
     launch-bound), in steady state with outputs reused across calls, as in a
-    stepping loop."""
+    stepping loop: per call from the host (us) and replayed from a captured
+    graph (graph_us, the launch chain alone)."""
     n = s["n"]
     small = {}
     rng = np.random.default_rng(1)
@@ -145,14 +166,16 @@ def small_blocks_leg(nb, ctx, dev, s, xp, vp, m, cap, precs):
         ent = {}
         for prec in precs:
             o = nb.regular_force(xp, vp, m, bd, rd, cap, prec, ctx=ctx)
-            us = 1e3 * steady_ms(
-                lambda: nb.regular_force(xp, vp, m, bd, rd, cap, prec, out=o, ctx=ctx))
-            ent[prec] = {"us": round(us, 1),
+            call = lambda: nb.regular_force(xp, vp, m, bd, rd, cap, prec, out=o, ctx=ctx)
+            us = 1e3 * steady_ms(call)
+            gus = 1e3 * graph_ms(call)
+            ent[prec] = {"us": round(us, 1), "graph_us": round(gus, 1),
                          "gpairs_per_s": round(size * (n - 1) / us * 1e-3, 2),
                          "jset_GB_per_s": round(56.0 * n / us * 1e-3, 1),
                          "plan": ctx.last_plan()}
         small[str(size)] = ent
-        log(f"small block n_i={size}: " + " ".join(f"{pp}={ent[pp]['us']} us" for pp in precs))
+        log(f"small block n_i={size}: " + " ".join(
+            f"{pp}={ent[pp]['us']} us (graph {ent[pp]['graph_us']} us)" for pp in precs))
     return small
 
 

@@ -161,6 +161,11 @@ int nb_predict(nb_ctx *ctx, int64_t n, double t, const double *x, const double *
  * running sums, with FP64 cross-split reduction; pairs closer than two
  * neighbour radii are evaluated in FP64, and rows whose rounding-error
  * estimate is too large are recomputed in FP64 (nb_ctx_set_mixed_tolerance).
+ * Small blocks (n_i <= 128 under automatic plans) are latency-bound, and an
+ * NB_MIXED request on them runs the FP64 kernels instead: no slower there,
+ * no refinement, and results to the FP64 bar (nb_ctx_last_plan then reads
+ * "prec=fp64 requested=mixed"; a plan set by nb_ctx_set_plan keeps the
+ * mixed kernels).
  * Outputs: acc, jerk [3][n_i] FP64; nb_count [n_i] (true count); nb_list
  * [n_i][nb_cap] row-major (first min(count, nb_cap) entries of a row are
  * defined); *overflow (required) = 1 iff some count > nb_cap, else 0;
@@ -269,10 +274,12 @@ int nb_autotune_batched(nb_ctx *ctx, int32_t n_clusters, const int64_t *j_off_ho
 
 /* Autotuner: times the candidate plans (rows per lane, splits, mapping) on
  * synthetic Plummer-like data for a ladder of block sizes at the given n,
- * for both precisions, and stores the fastest per (precision, n bucket, n_i
- * bucket).  If cache_path names a readable file written by an earlier run,
- * the table is loaded from it instead (flags & 1 forces re-tuning); after
- * tuning the table is written there.  Synchronises the device. */
+ * for both precisions (for NB_MIXED blocks of up to 256 rows, also the FP64
+ * kernels), and stores the fastest per (precision, n bucket, n_i bucket).
+ * If cache_path names a readable file written by an earlier run (text, first
+ * line "nbreg-tune 2"), the table is loaded from it instead (flags & 1
+ * forces re-tuning); after tuning the table is written there.  Synchronises
+ * the device. */
 int nb_autotune(nb_ctx *ctx, int64_t n, const char *cache_path, int flags);
 
 /* ---- the rest of the block step ---------------------------------------- */

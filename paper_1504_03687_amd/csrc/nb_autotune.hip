@@ -67,17 +67,19 @@ static int load_table(nb_ctx *ctx, const char *path, int64_t n_bucket, bool *fou
     FILE *f = std::fopen(path, "r");
     if (!f) return NB_OK;
     char head[64] = {0};
-    if (!std::fgets(head, sizeof head, f) || std::strncmp(head, "nbreg-tune 1", 12) != 0) {
+    if (!std::fgets(head, sizeof head, f) || std::strncmp(head, "nbreg-tune 2", 12) != 0) {
         std::fclose(f);
         return NB_OK;
     }
-    int prec, mapping, rows, splits;
+    int prec, mapping, rows, splits, f64;
     long long nb, nib;
-    while (std::fscanf(f, "%d %lld %lld %d %d %d", &prec, &nb, &nib, &mapping, &rows, &splits) == 6) {
+    while (std::fscanf(f, "%d %lld %lld %d %d %d %d", &prec, &nb, &nib, &mapping, &rows, &splits,
+                       &f64) == 7) {
         if (mapping < 1 || mapping > 2 || splits < 1 ||
-            !(rows == 1 || rows == 2 || rows == 4))
+            !(rows == 1 || rows == 2 || rows == 4) || f64 < 0 || f64 > 1)
             continue;
-        ctx->tuned[std::make_tuple(prec, (int64_t)nb, (int64_t)nib)] = nb::Plan{mapping, rows, splits};
+        ctx->tuned[std::make_tuple(prec, (int64_t)nb, (int64_t)nib)] =
+            nb::Plan{mapping, rows, splits, prec == 1 ? f64 : 0};
         if (nb == n_bucket) *found = true;
     }
     std::fclose(f);
@@ -161,13 +163,23 @@ extern "C" int nb_autotune(nb_ctx *ctx, int64_t n, const char *cache_path, int f
                     for (int64_t sc : {base / 2, base, base * 2}) {
                         const int64_t maxs = max_splits(n, mapping);
                         const int s = (int)std::max<int64_t>(1, std::min<int64_t>(sc, maxs));
-                        nb::Plan p{mapping, rows, s};
+                        nb::Plan p{mapping, rows, s, 0};
                         bool dup = false;
                         for (auto &q : cands)
                             dup |= q.mapping == p.mapping && q.rows_per_lane == p.rows_per_lane &&
                                    q.splits == p.splits;
                         if (!dup) cands.push_back(p);
                     }
+                }
+            }
+            // a mixed request on a small block may be served faster by the
+            // FP64 kernels (latency-bound, and no refinement)
+            if (prec == 1 && ni <= 256) {
+                const size_t k = cands.size();
+                for (size_t q = 0; q < k; ++q) {
+                    nb::Plan p = cands[q];
+                    p.f64 = 1;
+                    cands.push_back(p);
                 }
             }
             float best_ms = 1e30f;
@@ -217,11 +229,12 @@ extern "C" int nb_autotune(nb_ctx *ctx, int64_t n, const char *cache_path, int f
     if (cache_path) {
         FILE *f = std::fopen(cache_path, "w");
         if (f) {
-            std::fprintf(f, "nbreg-tune 1\n");
+            std::fprintf(f, "nbreg-tune 2\n");
             for (auto &kv : ctx->tuned)
-                std::fprintf(f, "%d %lld %lld %d %d %d\n", std::get<0>(kv.first),
+                std::fprintf(f, "%d %lld %lld %d %d %d %d\n", std::get<0>(kv.first),
                              (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
-                             kv.second.mapping, kv.second.rows_per_lane, kv.second.splits);
+                             kv.second.mapping, kv.second.rows_per_lane, kv.second.splits,
+                             kv.second.f64);
             std::fclose(f);
         }
     }

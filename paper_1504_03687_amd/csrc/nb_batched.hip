@@ -338,10 +338,10 @@ static int build_cache(nb_ctx *ctx, BatchedCache *c, const nb::ForceArgs &f, boo
     if (e != hipSuccess) return hip_fail(ctx, e);
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = nb::launch_fill_i32(queue, 0, 1, cs);
+        // the queue's block holds the work counter, the refinement counter
+        // and the refinement's arrival word (which also resets itself)
+        hipError_t le = nb::launch_fill_i32(queue, 0, 64, cs);
         if (le == hipSuccess) le = nb::launch_fill_i32(f.overflow, 0, 1, cs);
-        if (le == hipSuccess && c->redo_k > 0.0)
-            le = nb::launch_fill_i32(A.f.redo_count, 0, 1, cs);
         if (le == hipSuccess) le = nb::launch_batched(mixed, c->shape, c->grid, A, cs);
         if (le == hipSuccess) le = nb::launch_batched_merge(A, cs);
         if (le == hipSuccess && c->redo_k > 0.0)

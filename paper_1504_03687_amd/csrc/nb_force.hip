@@ -30,11 +30,23 @@ namespace nb {
 
 namespace {
 
+// A split launch zeroes the call's overflow word and refinement counter
+// itself (its rows go to split slots, so nothing in it touches those words;
+// the merge launch after it is the first to write them).
+__device__ __forceinline__ void clear_call_words(const ForceArgs &a)
+{
+    if (a.clear0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        *a.clear0 = 0;
+        if (a.clear1) *a.clear1 = 0;
+    }
+}
+
 // grid = (ceil(n_i / (IR * kBlock)), splits)
 template <bool MIXED, int IR>
 __global__ __launch_bounds__(kBlock) void force_rows_kernel(ForceArgs a)
 {
     __shared__ JBody tile[2][kTile];
+    clear_call_words(a);
     const int32_t split = blockIdx.y;
     const int64_t j0 = (int64_t)split * a.split_len;
     const int64_t j1 = j0 + a.split_len < a.n ? j0 + a.split_len : a.n;
@@ -43,18 +55,21 @@ __global__ __launch_bounds__(kBlock) void force_rows_kernel(ForceArgs a)
                          a.near_factor);
 }
 
-// Wave w (global) handles row group w / splits (rows G*(w/splits) + g) over
-// j-range w % splits.  grid = ceil(waves / 4).
+// Wave w (global) handles row group w % ngroups (rows G*(w%ngroups) + g) over
+// j-range w / ngroups.  The row groups of one j-range are consecutive waves,
+// mostly of one work-group, so the groups after the first read that range
+// from cache, not from memory.  grid = ceil(waves / 4).
 template <bool MIXED, int G>
 __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t gw = (int64_t)blockIdx.x * (kBlock / kWave) +
                        __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    clear_call_words(a);
     const int64_t ngroups = (a.n_i + G - 1) / G;
     if (gw >= ngroups * a.splits) return;   // whole wave leaves together
-    const int64_t group = gw / a.splits;
-    const int32_t split = (int32_t)(gw - group * a.splits);
+    const int32_t split = (int32_t)(gw / ngroups);
+    const int64_t group = gw - (int64_t)split * ngroups;
     const int64_t j0 = (int64_t)split * a.split_len;
     const int64_t j1 = j0 + a.split_len < a.n ? j0 + a.split_len : a.n;
     const Dest d{a.splits == 1, (int64_t)split, 0, (int64_t)a.splits};
@@ -102,13 +117,22 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
         }
     }
 
+    // the bodies of the next D iterations are loaded ahead (a ring of D
+    // registers), so D loads per lane are in flight while one is computed:
+    // with few rows per wave the loop is bound by memory latency
+    constexpr int D = G == 1 ? 4 : 2;
     int iter = 0;
-    JBody Jn;
-    load_body(Jn, a, j0 + lane, j1);
-    for (int64_t base = j0; base < j1; base += kWave) {
+    JBody Jq[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) load_body(Jq[u], a, j0 + u * kWave + lane, j1);
+    for (int64_t base0 = j0; base0 < j1; base0 += D * kWave) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        const int64_t base = base0 + u * kWave;
+        if (base >= j1) break;   // uniform
         const int64_t j = base + lane;
-        const JBody J = Jn;
-        if (base + kWave < j1) load_body(Jn, a, j + kWave, j1);   // prefetch
+        const JBody J = Jq[u];
+        if (base + D * kWave < j1) load_body(Jq[u], a, j + D * kWave, j1);
         const int32_t jidx = (int32_t)j;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -161,19 +185,34 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
             }
         }
     }
-    bool ovf = false, bad = false, nonfin = false;
+    }
+    // the wave sums of all rows' eight components in one butterfly pass
+    double r[G * 8];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         S[g].fold();
+        r[g * 8 + 0] = S[g].ax;
+        r[g * 8 + 1] = S[g].ay;
+        r[g * 8 + 2] = S[g].az;
+        r[g * 8 + 3] = S[g].jx;
+        r[g * 8 + 4] = S[g].jy;
+        r[g * 8 + 5] = S[g].jz;
+        r[g * 8 + 6] = S[g].va;
+        r[g * 8 + 7] = S[g].vj;
+    }
+    group_sums<kWave, G * 8>(r);
+    bool ovf = false, bad = false, nonfin = false;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
         Sums<MIXED> T = S[g];
-        T.ax = wave_sum(T.ax);
-        T.ay = wave_sum(T.ay);
-        T.az = wave_sum(T.az);
-        T.jx = wave_sum(T.jx);
-        T.jy = wave_sum(T.jy);
-        T.jz = wave_sum(T.jz);
-        T.va = wave_sum(T.va);
-        T.vj = wave_sum(T.vj);
+        T.ax = r[g * 8 + 0];
+        T.ay = r[g * 8 + 1];
+        T.az = r[g * 8 + 2];
+        T.jx = r[g * 8 + 3];
+        T.jy = r[g * 8 + 4];
+        T.jz = r[g * 8 + 5];
+        T.va = r[g * 8 + 6];
+        T.vj = r[g * 8 + 7];
         const int64_t b = group * G + g;
         if (lane == 0 && b < a.n_i) {
             bool o = false, bd = false, f = false;
@@ -202,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(ForceArgs a)
 __global__ __launch_bounds__(kBlock) void merge_wg_kernel(ForceArgs a)
 {
     __shared__ double lds[kSlotComp][kBlock / kWave];
-    __shared__ int64_t scan[kBlock];
+    __shared__ int64_t scan[kBlock / kWave];
     const int64_t b = blockIdx.x;
     const MergeGeom g{a.splits, b * a.splits, 1, 0, a.n, a.split_len};
     merge_row_wg(a, b, g, lds, scan);
@@ -218,21 +257,27 @@ __device__ __forceinline__ void write_forces(const ForceArgs &a, int64_t b, cons
     a.jerk[2 * (int64_t)a.n_i + b] = v[5];
 }
 
-// Refinement, pass 1: the first redo_rcap listed rows as (row group, chunk)
-// items over the whole grid (chunk partials to scratch); any further rows one
-// work-group each, chunks in order.  Both give the same chunk-ordered sum.
-// A group is kRedoRows consecutive listed rows: when they share one j-range
-// (always in a single-block call) they are summed together, each body loaded
-// once; otherwise row by row.  Chunks past a row's own range are skipped.
-__global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
+// Refinement of the listed rows in one launch.  Pass 1: the first redo_rcap
+// listed rows as (row group, chunk) items over the whole grid (chunk partials
+// to scratch); any further rows one work-group each, chunks in order.  Pass 2:
+// the work-group that finishes pass 1 last adds each buffered row's chunk
+// partials in chunk order and overwrites its forces.  Both routes give the
+// same chunk-ordered sum.  A group is kRedoRows consecutive listed rows: when
+// they share one j-range (always in a single-block call) they are summed
+// together, each body loaded once; otherwise row by row.  Chunks past a row's
+// own range are skipped.  With no listed row every work-group leaves at once
+// (no fence, no atomic), which is the common case of small blocks.
+__global__ __launch_bounds__(kBlock) void redo_kernel(ForceArgs a)
 {
     __shared__ double lds[kRedoRows * 6][kBlock / kWave];
-    const int32_t count = __builtin_amdgcn_readfirstlane(*(volatile int32_t *)a.redo_count);
+    __shared__ int32_t last;
+    const int32_t count = load_word_uniform(a.redo_count);
+    if (count == 0) return;
     const int32_t par = count < a.redo_rcap ? count : a.redo_rcap;
     const int32_t C = a.redo_chunks;
     const int32_t G = (par + kRedoRows - 1) / kRedoRows;
     const int64_t items = (int64_t)G * C;
-    double v[kRedoRows * 6];
+    double v[kRedoRows * 6], v1[6];
     // chunk-major order: work-groups running at the same time share a chunk
     // of bodies (L2 reuse across the refined rows)
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
@@ -253,10 +298,10 @@ __global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
             for (int r = 0; r < nr; ++r) {
                 const int32_t q = q0 + r;
                 if (c >= redo_row_chunks(a, q)) continue;
-                redo_chunk(a, q, c, lds, v);
+                redo_chunk(a, q, c, lds, v1);
                 if (threadIdx.x == 0)
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) a.redo_part[((int64_t)q * C + c) * 6 + k] = v[k];
+                    for (int k = 0; k < 6; ++k) a.redo_part[((int64_t)q * C + c) * 6 + k] = v1[k];
             }
         }
     }
@@ -264,30 +309,35 @@ __global__ __launch_bounds__(kBlock) void redo_part_kernel(ForceArgs a)
         double acc[6] = {0, 0, 0, 0, 0, 0};
         const int32_t nc = redo_row_chunks(a, (int32_t)q);
         for (int32_t c = 0; c < nc; ++c) {
-            redo_chunk(a, (int32_t)q, c, lds, v);
+            redo_chunk(a, (int32_t)q, c, lds, v1);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc[k] += v[k];
+            for (int k = 0; k < 6; ++k) acc[k] += v1[k];
         }
         if (threadIdx.x == 0) write_forces(a, a.redo_rows[q], acc);
     }
-}
+    if (par == 0) return;   // nothing buffered (uniform over the grid)
 
-// Refinement, pass 2: sum each buffered row's chunks in order and overwrite
-// its forces.
-__global__ __launch_bounds__(256) void redo_final_kernel(ForceArgs a)
-{
-    const int32_t count = *(volatile int32_t *)a.redo_count;
-    const int32_t par = count < a.redo_rcap ? count : a.redo_rcap;
-    const int32_t C = a.redo_chunks;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < par;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        double v[6] = {0, 0, 0, 0, 0, 0};
-        const int32_t nc = redo_row_chunks(a, (int32_t)q);
+    // arrival: the chunk partials were written by lane 0, which publishes
+    // them device-wide before it counts this work-group in
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(a.redo_arrive, 1) == (int32_t)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();   // every work-group's partials are visible from here
+    for (int32_t q = threadIdx.x; q < par; q += blockDim.x) {
+        double s[6] = {0, 0, 0, 0, 0, 0};
+        const int32_t nc = redo_row_chunks(a, q);
+        const double *p = a.redo_part + (int64_t)q * C * 6;
+#pragma unroll 4
         for (int32_t c = 0; c < nc; ++c)
 #pragma unroll
-            for (int k = 0; k < 6; ++k) v[k] += a.redo_part[(q * C + c) * 6 + k];
-        write_forces(a, a.redo_rows[q], v);
+            for (int k = 0; k < 6; ++k) s[k] += p[c * 6 + k];
+        write_forces(a, a.redo_rows[q], s);
     }
+    if (threadIdx.x == 0) *a.redo_arrive = 0;   // every work-group has arrived
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int32_t value, int64_t count)
@@ -350,6 +400,7 @@ void bind_redo_scratch(ForceArgs &a, void *base, int32_t *counter, int32_t group
     char *p = (char *)base;
     const size_t arr = round256((size_t)(a.n_i > 0 ? a.n_i : 1) * sizeof(int32_t));
     a.redo_count = counter;
+    a.redo_arrive = counter + 16;   // its own 64 bytes; zero when the words are created
     a.redo_rows = (int32_t *)p;
     a.redo_j0 = (int32_t *)(p + arr);
     a.redo_j1 = (int32_t *)(p + 2 * arr);
@@ -361,10 +412,12 @@ void bind_redo_scratch(ForceArgs &a, void *base, int32_t *counter, int32_t group
 
 hipError_t launch_redo(const ForceArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(redo_part_kernel, dim3((unsigned)a.redo_groups), dim3(kBlock), 0, s, a);
-    const int64_t rows = a.n_i > 0 ? a.n_i : 1;
-    hipLaunchKernelGGL(redo_final_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s,
-                       a);
+    // no more work-groups than the most items a call of n_i rows can list
+    const int64_t rows = std::max<int64_t>(a.n_i, 1);
+    const int64_t par = std::min<int64_t>(rows, a.redo_rcap);
+    const int64_t items = (par + kRedoRows - 1) / kRedoRows * a.redo_chunks + (rows - par);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(a.redo_groups, items));
+    hipLaunchKernelGGL(redo_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

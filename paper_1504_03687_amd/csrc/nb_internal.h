@@ -43,6 +43,11 @@ struct ForceArgs {
     int32_t *nb_count, *nb_list;
     int32_t *overflow;
     uint32_t *status;
+    // words the force kernel zeroes as it starts (null: none).  Set only for
+    // split launches, whose force kernel writes neither the overflow word nor
+    // the refinement counter (the merge does), so no separate clearing launch
+    // is needed.
+    int32_t *clear0, *clear1;
     // split layout: split s covers j in [s * split_len, min(n, (s+1) * split_len))
     int32_t splits;
     int64_t split_len;
@@ -57,6 +62,8 @@ struct ForceArgs {
     // (row, j-range) to the redo list and recomputed in FP64 afterwards
     double redo_k;        // 2^-24 * safety / tolerance; 0 disables
     int32_t *redo_count;  // device counter, zeroed before the force kernel
+    int32_t *redo_arrive; // work-groups done with the first refinement pass;
+                          // zero between calls (the last arrival resets it)
     int32_t *redo_rows;   // [n_i]
     int32_t *redo_j0, *redo_j1;
     float near_factor;    // mixed: FP64 near field below near_factor * rs2
@@ -89,6 +96,7 @@ struct Plan {
     int mapping;        // 1 = row per lane (LDS j-tiles), 2 = row group per wave
     int rows_per_lane;  // mapping 1: 1, 2, 4;  mapping 2: rows per wave 1, 2, 4
     int splits;         // j-ranges (mapping 1: per work-group; mapping 2: per wave)
+    int f64;            // 1: a mixed-precision request runs the FP64 kernels
 };
 
 // Scratch bytes needed for a plan (0 when splits == 1).

@@ -74,6 +74,16 @@ int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, i
 constexpr int32_t kWaveMaxRowsMixed = 128;
 constexpr int32_t kWaveMaxRowsF64 = 192;
 
+// Largest block whose mixed-precision request runs the FP64 kernels in the
+// automatic plan.  Small blocks are bound by memory latency, not arithmetic,
+// so the FP64 wave kernel is no slower than the mixed one, and it needs no
+// refinement launch (nor, for a flagged row, the refinement itself).  Whole
+// call, N = 2^20 (steady state), mixed vs FP64 kernels: 1 row 22.7 vs 20.4
+// us, 8 rows 36.7 vs 31.4, 32 rows 124.7 (one row refined) vs 67.3, 64 rows
+// 155 vs 137, 128 rows 270 vs 238; at 192 rows the mixed row-per-lane kernel
+// is ahead (232 vs 338 us).  The results then meet the FP64 bar.
+constexpr int32_t kMixedAsF64MaxRows = 128;
+
 // Automatic plan for a block of n_i rows against n bodies: the autotuned
 // entry for the size buckets if there is one, else the wave mapping for
 // small blocks and one row per lane above.
@@ -81,6 +91,11 @@ Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed)
 {
     auto it = ctx->tuned.find(std::make_tuple((int)mixed, bucket_log2(n), bucket_log2(n_i)));
     if (it != ctx->tuned.end()) return it->second;
+    if (mixed && n_i <= kMixedAsF64MaxRows) {
+        Plan p = auto_plan(ctx, n, n_i, false);
+        p.f64 = 1;
+        return p;
+    }
     Plan p{};
     if (n_i <= (mixed ? kWaveMaxRowsMixed : kWaveMaxRowsF64)) {
         p.mapping = 2;

@@ -362,13 +362,6 @@ __device__ __forceinline__ void rows_pass(const ForceArgs &a, JBody (*tile)[T], 
     flush_flags(a, ovf, bad, nonfin);
 }
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
 // Geometry of one row's splits for the merge.
 struct MergeGeom {
     int32_t splits;
@@ -377,14 +370,31 @@ struct MergeGeom {
     int64_t j_begin, j_end, split_len;
 };
 
-// Sum over the W aligned lanes of a lane group (butterfly, largest offset
-// first; every lane of the group gets the result).
-template <int W>
-__device__ __forceinline__ double group_sum(double v)
+// Sums of K values over the W aligned lanes of a lane group (butterfly,
+// largest offset first; every lane of the group gets the results).  The
+// butterflies run level by level across the K values, so the K shuffles of a
+// level are issued together and a level waits on one cross-lane permute
+// latency instead of K (value after value, eight values took about 2 us).
+// Each value gets the pairs and order of its own butterfly.
+template <int W, int K>
+__device__ __forceinline__ void group_sums(double (&v)[K])
 {
 #pragma unroll
-    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    for (int o = W / 2; o > 0; o >>= 1) {
+        double t[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) t[k] = __shfl_xor(v[k], o, kWave);
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += t[k];
+    }
+}
+
+// A word written by an earlier launch (a counter), read at a uniform address
+// through the scalar cache: many work-groups reading one word this way do
+// not queue on one memory channel, as uncached vector loads of it do.
+__device__ __forceinline__ int32_t load_word_uniform(const int32_t *p)
+{
+    return *(const __attribute__((address_space(4))) int32_t *)p;
 }
 
 // Lanes per row of the single-wave merge for a given split count: the next of
@@ -425,8 +435,7 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, bool ha
             v[2 * k + 1] += t.y;
         }
     }
-#pragma unroll
-    for (int k = 0; k < kSlotComp; ++k) v[k] = group_sum<W>(v[k]);
+    group_sums<W, kSlotComp>(v);
 
     bool ovf = false, nonfin = false;
     if (bad) {
@@ -516,10 +525,9 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, bool ha
 // must call it): each value is summed over its wave by a butterfly, then the
 // four wave sums are added in wave order; every lane gets the results.
 template <int K>
-__device__ __forceinline__ void block_sums(double v[K], double (*lds)[kBlock / kWave])
+__device__ __forceinline__ void block_sums(double (&v)[K], double (*lds)[kBlock / kWave])
 {
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    group_sums<kWave, K>(v);
     const int w = threadIdx.x / kWave;
     __syncthreads();   // earlier readers of lds are done
     if ((threadIdx.x & (kWave - 1)) == 0)
@@ -546,7 +554,7 @@ __device__ __forceinline__ int32_t redo_row_chunks(const ForceArgs &a, int32_t q
 // work-group in a fixed pattern; every lane gets the six sums (acc, jerk).
 // The chunk must lie inside the row's j-range (c < redo_row_chunks).
 __device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_t c,
-                                          double (*lds)[kBlock / kWave], double out[6])
+                                          double (*lds)[kBlock / kWave], double (&out)[6])
 {
     const int64_t b = a.redo_rows[q];
     const int64_t j0 = a.redo_j0[q], j1 = a.redo_j1[q];
@@ -591,7 +599,7 @@ constexpr int kRedoRows = 2;
 // the j-range of row q0 and c < its chunk count; out[r][k] for row q0 + r.
 __device__ __forceinline__ void redo_chunk_rows(const ForceArgs &a, int32_t q0, int nr, int32_t c,
                                                double (*lds)[kBlock / kWave],
-                                               double out[kRedoRows * 6])
+                                               double (&out)[kRedoRows * 6])
 {
     const int64_t j0 = a.redo_j0[q0], j1 = a.redo_j1[q0];
     const int64_t cj0 = j0 + (int64_t)c * kRedoChunk;
@@ -649,116 +657,191 @@ __device__ __forceinline__ void redo_chunk_rows(const ForceArgs &a, int32_t q0, 
 }
 
 constexpr int kMergeBatch = 8;    // strides of split partials loaded per batch
-constexpr int kCountBatch = 16;   // segment counts loaded per batch
+constexpr int kCountBatch = 8;    // segment counts loaded per batch
 
-// Merge of one row by a whole work-group, for plans with many splits: the
-// sums stride the splits over the lanes (fixed order); for the lists lane t
-// owns the contiguous splits [t*K, (t+1)*K) and a work-group prefix scan of
-// the lanes' counts places its segments, so the list stays in split order.
+// Copies entries [from, take) of the neighbour segment of split s (count c)
+// to dst: from its slot, or, for an overflowed segment, by rescanning the
+// split's j-range in order.
+__device__ __forceinline__ void copy_segment(const ForceArgs &a, const MergeGeom &g, int64_t b,
+                                             int64_t i, int32_t s, int32_t c, int64_t from,
+                                             int64_t take, int32_t *dst)
+{
+    const int64_t slot = g.slot0 + (int64_t)s * g.slot_step;
+    if (c <= kSegCap) {
+        const int32_t *src = a.seg_list + slot * kSegCap;
+        for (int64_t q = from; q < take; ++q) dst[q] = src[q];
+        return;
+    }
+    const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
+    const float rs2f = (float)a.rs2[b];
+    const int64_t jb = g.j_begin + (int64_t)s * g.split_len;
+    const int64_t je = jb + g.split_len < g.j_end ? jb + g.split_len : g.j_end;
+    int64_t placed = 0;
+    for (int64_t j = jb; j < je && placed < take; ++j) {
+        if (j == i) continue;
+        const double dx = a.xp[j] - xi, dy = a.xp[a.n + j] - yi, dz = a.xp[2 * a.n + j] - zi;
+        if (canon_r2f(dx, dy, dz) < rs2f) {
+            if (placed >= from) dst[placed] = (int32_t)j;
+            ++placed;
+        }
+    }
+}
+
+// Partial records of splits sb + u * kBlock (u < kMergeBatch) of one row;
+// past the last split, split 0's record is loaded (and not added).
+__device__ __forceinline__ void merge_load_batch(const ForceArgs &a, const MergeGeom &g,
+                                                 int32_t sb, double (&t)[kMergeBatch][kSlotComp])
+{
+#pragma unroll
+    for (int u = 0; u < kMergeBatch; ++u) {
+        const int32_t s = sb + u * kBlock;
+        const double2 *p = slot_rec(a, g.slot0 + (int64_t)(s < g.splits ? s : 0) * g.slot_step);
+#pragma unroll
+        for (int k = 0; k < kSlotComp / 2; ++k) {
+            const double2 q = p[k];
+            t[u][2 * k] = q.x;
+            t[u][2 * k + 1] = q.y;
+        }
+    }
+}
+
+__device__ __forceinline__ void merge_add_batch(int32_t S, int32_t sb,
+                                                const double (&t)[kMergeBatch][kSlotComp],
+                                                double (&v)[kSlotComp])
+{
+#pragma unroll
+    for (int u = 0; u < kMergeBatch; ++u)
+        if (sb + u * kBlock < S) {
+#pragma unroll
+            for (int k = 0; k < kSlotComp; ++k) v[k] += t[u][k];
+        }
+}
+
+// Merge of one row by a whole work-group, for plans with many splits.  The
+// sums stride the splits over the lanes (fixed order: a lane adds its splits
+// in increasing order, then the wave butterfly, then the four wave sums in
+// wave order).  For the list, lane t owns the contiguous splits [t*K,
+// (t+1)*K), and a work-group prefix scan of the lanes' counts places its
+// segments, so the list stays in split order.  The work is laid out for few
+// memory round trips: a lane's counts are loaded with its partials, and the
+// first two entries of all its segments are loaded before any is stored.
+// Called once per work-group (its LDS arrays are not reused).
 __device__ __forceinline__ void merge_row_wg(const ForceArgs &a, int64_t b, const MergeGeom &g,
                                              double (*lds)[kBlock / kWave], int64_t *scan)
 {
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), w = tid / kWave;
     const int64_t i = a.i_block[b];
     const bool bad = i < 0 || i >= a.n;
     const int32_t S = g.splits;
     const int32_t K = (S + kBlock - 1) / kBlock;
     const int32_t s0 = tid * K;
-    const int32_t s1 = s0 + K < S ? s0 + K : S;
+    const int32_t nmine = s0 < S ? (S - s0 < K ? S - s0 : K) : 0;
 
-    // sums: lanes stride the splits (coalesced loads), fixed order; the loads
-    // of kMergeBatch strides are issued before any is added, so a lane waits
-    // on one memory latency per batch, not per split
+    // sums: the loads of kMergeBatch strides are issued before any is added,
+    // so a lane waits on one memory latency per batch, not per split.  The
+    // first batch is issued ahead of the lane's first kCountBatch counts (the
+    // memory counter waits in issue order), so both arrive in one round trip.
     double v[kSlotComp] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int32_t sb = tid; sb < S; sb += kBlock * kMergeBatch) {
-        double t[kMergeBatch][kSlotComp];
+    double t[kMergeBatch][kSlotComp];
+    merge_load_batch(a, g, tid, t);
+    int32_t ck[kCountBatch];
 #pragma unroll
-        for (int u = 0; u < kMergeBatch; ++u) {
-            const int32_t s = sb + u * kBlock;
-            const double2 *p = slot_rec(a, g.slot0 + (int64_t)(s < S ? s : 0) * g.slot_step);
-#pragma unroll
-            for (int k = 0; k < kSlotComp / 2; ++k) {
-                const double2 q = p[k];
-                t[u][2 * k] = q.x;
-                t[u][2 * k + 1] = q.y;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kMergeBatch; ++u)
-            if (sb + u * kBlock < S) {
-#pragma unroll
-                for (int k = 0; k < kSlotComp; ++k) v[k] += t[u][k];
-            }
+    for (int u = 0; u < kCountBatch; ++u) {
+        const int32_t s = s0 + u < S ? s0 + u : S - 1;   // in range; unused past nmine
+        const int32_t c = a.seg_cnt[g.slot0 + (int64_t)s * g.slot_step];
+        ck[u] = u < nmine ? c : 0;
     }
-    // counts: lane t owns the contiguous splits [s0, s1) so that its segments
-    // are consecutive in the row's list; nz marks its non-empty segments
-    // (first 64), so the copy below visits only those
+    merge_add_batch(S, tid, t, v);
+    for (int32_t sb = tid + kBlock * kMergeBatch; sb < S; sb += kBlock * kMergeBatch) {
+        merge_load_batch(a, g, sb, t);
+        merge_add_batch(S, sb, t, v);
+    }
     int64_t mine = 0;
-    uint64_t nz = 0;
-    for (int32_t sb = s0; sb < s1; sb += kCountBatch) {
+#pragma unroll
+    for (int u = 0; u < kCountBatch; ++u) mine += ck[u];
+    for (int32_t sb = kCountBatch; sb < nmine; sb += kCountBatch) {   // K > kCountBatch
         int32_t c[kCountBatch];
 #pragma unroll
         for (int u = 0; u < kCountBatch; ++u) {
-            const int32_t s = sb + u < s1 ? sb + u : s0;
+            const int32_t s = sb + u < nmine ? s0 + sb + u : s0;
             c[u] = a.seg_cnt[g.slot0 + (int64_t)s * g.slot_step];
         }
 #pragma unroll
-        for (int u = 0; u < kCountBatch; ++u)
-            if (sb + u < s1) {
-                mine += c[u];
-                if (c[u] > 0 && sb + u - s0 < 64) nz |= 1ull << (sb + u - s0);
-            }
+        for (int u = 0; u < kCountBatch; ++u) mine += sb + u < nmine ? c[u] : 0;
     }
-    block_sums<kSlotComp>(v, lds);
 
-    // exclusive scan of the lanes' neighbour counts (Hillis-Steele in LDS)
-    __syncthreads();
-    scan[tid] = mine;
-    __syncthreads();
-    for (int o = 1; o < kBlock; o <<= 1) {
-        const int64_t add = tid >= o ? scan[tid - o] : 0;
-        __syncthreads();
-        scan[tid] += add;
-        __syncthreads();
+    // one barrier for both reductions: wave butterflies of the sums and a
+    // wave scan of the counts, then the four waves' values from LDS
+    group_sums<kWave, kSlotComp>(v);
+    int64_t inc = mine;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int64_t t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
     }
-    const int64_t total = scan[kBlock - 1];
-    int64_t start = scan[tid] - mine;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < kSlotComp; ++k) lds[k][w] = v[k];
+    if (lane == kWave - 1) scan[w] = inc;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSlotComp; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kBlock / kWave; ++q) t += lds[k][q];
+        v[k] = t;
+    }
+    int64_t before = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / kWave; ++q) {
+        const int64_t t = scan[q];
+        total += t;
+        before += q < w ? t : 0;
+    }
+    const int64_t start = before + inc - mine;
 
     bool ovf = false, nonfin = false;
     if (!bad) {
-        const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
-        const float rs2f = (float)a.rs2[b];
-        // with at most 64 splits per lane only the marked segments are read
-        uint64_t todo = nz;
-        int32_t s = s0 - 1;
-        while (start < a.cap) {
-            if (K <= 64) {
-                if (!todo) break;
-                s = s0 + __builtin_ctzll(todo);
-                todo &= todo - 1;
-            } else if (++s >= s1) {
-                break;
-            }
-            const int64_t slot = g.slot0 + (int64_t)s * g.slot_step;
-            const int32_t c = a.seg_cnt[slot];
-            if (c <= 0) continue;
-            const int64_t take = (int64_t)c < a.cap - start ? c : a.cap - start;
-            int32_t *dst = a.nb_list + b * (int64_t)a.cap + start;
-            if (c <= kSegCap) {
-                const int32_t *src = a.seg_list + slot * kSegCap;
-                for (int64_t q = 0; q < take; ++q) dst[q] = src[q];
-            } else {   // overflowed segment: rescan its j-range, in order
-                const int64_t jb = g.j_begin + (int64_t)s * g.split_len;
-                const int64_t je = jb + g.split_len < g.j_end ? jb + g.split_len : g.j_end;
-                int64_t placed = 0;
-                for (int64_t j = jb; j < je && placed < take; ++j) {
-                    if (j == i) continue;
-                    const double dx = a.xp[j] - xi, dy = a.xp[a.n + j] - yi,
-                                 dz = a.xp[2 * a.n + j] - zi;
-                    if (canon_r2f(dx, dy, dz) < rs2f) dst[placed++] = (int32_t)j;
+        // the lane's segments in batches of kCountBatch: the first two
+        // entries of every segment of a batch are loaded before any is stored
+        int32_t *row = a.nb_list + b * (int64_t)a.cap;
+        int64_t at = start;
+        for (int32_t sb = 0; sb < nmine && at < a.cap; sb += kCountBatch) {
+            if (sb > 0) {
+#pragma unroll
+                for (int u = 0; u < kCountBatch; ++u) {
+                    const int32_t s = sb + u < nmine ? s0 + sb + u : s0;
+                    const int32_t c = a.seg_cnt[g.slot0 + (int64_t)s * g.slot_step];
+                    ck[u] = sb + u < nmine ? c : 0;
                 }
             }
-            start += c;
+            int32_t e0[kCountBatch], e1[kCountBatch];
+            int64_t p = at;
+#pragma unroll
+            for (int u = 0; u < kCountBatch; ++u) {
+                const int32_t *src =
+                    a.seg_list + (g.slot0 + (int64_t)(s0 + sb + u) * g.slot_step) * kSegCap;
+                const bool ok = ck[u] > 0 && ck[u] <= kSegCap && p < a.cap;
+                e0[u] = ok ? src[0] : 0;
+                e1[u] = ok && ck[u] > 1 && p + 1 < a.cap ? src[1] : 0;
+                p += ck[u];
+            }
+#pragma unroll
+            for (int u = 0; u < kCountBatch; ++u) {
+                const int32_t c = ck[u];
+                if (c > 0 && at < a.cap) {
+                    const int64_t take = (int64_t)c < a.cap - at ? c : a.cap - at;
+                    if (c <= kSegCap) {
+                        row[at] = e0[u];
+                        if (take > 1) row[at + 1] = e1[u];
+                        if (take > 2) copy_segment(a, g, b, i, s0 + sb + u, c, 2, take, row + at);
+                    } else {
+                        copy_segment(a, g, b, i, s0 + sb + u, c, 0, take, row + at);
+                    }
+                }
+                at += c;
+            }
         }
         if (tid == 0) {
             a.acc[b] = v[0];

@@ -194,6 +194,8 @@ int nb_ctx_create(nb_ctx **out, int device, void *hip_stream)
         (void)hipGetDevice(&prev);
         hipError_t e = hipSetDevice(device);
         if (e == hipSuccess) e = hipMalloc((void **)&ctx->words, 256);
+        // the refinement's arrival word must start at zero (it resets itself)
+        if (e == hipSuccess) e = hipMemset(ctx->words, 0, 256);
         if (e == hipSuccess) e = fixed_scratch_of(device, &ctx->fixed_scratch);
         (void)hipSetDevice(prev);
         if (e != hipSuccess) {
@@ -352,13 +354,14 @@ static int regular_force_impl(nb_ctx *ctx, int64_t n, const double *xp, const do
         std::snprintf(ctx->last_plan, sizeof ctx->last_plan, "empty");
         return NB_OK;
     }
-    const bool mixed = prec == NB_MIXED;
-    Plan p = auto_plan(ctx, n, n_i, mixed);
+    Plan p = auto_plan(ctx, n, n_i, prec == NB_MIXED);
     if (ctx->has_forced) {
         if (ctx->forced.mapping) p.mapping = ctx->forced.mapping;
         if (ctx->forced.rows_per_lane) p.rows_per_lane = ctx->forced.rows_per_lane;
         if (ctx->forced.splits) p.splits = ctx->forced.splits;
+        p.f64 = ctx->forced.f64;   // a forced plan runs the requested kernels
     }
+    const bool mixed = prec == NB_MIXED && !p.f64;
     int64_t split_len = 0;
     finish_plan(p, n, n_i, &split_len);
 
@@ -410,13 +413,20 @@ static int regular_force_impl(nb_ctx *ctx, int64_t n, const double *xp, const do
         base = ctx->scratch;
     }
     if (redo_bytes) nb::bind_redo_scratch(fa, base, ctx->words, groups, n, rcap_limit);
-    // the overflow word and the refinement counter start at zero (one launch)
-    e = nb::launch_clear_words(overflow, redo_bytes ? fa.redo_count : nullptr, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e);
+    // the overflow word and the refinement counter start at zero: zeroed by
+    // the force kernel of a split launch, else by one small launch first
+    if (p.splits > 1) {
+        fa.clear0 = overflow;
+        fa.clear1 = redo_bytes ? fa.redo_count : nullptr;
+    } else {
+        e = nb::launch_clear_words(overflow, redo_bytes ? fa.redo_count : nullptr, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e);
+    }
     nb::force_bind_scratch(fa, (char *)base + redo_bytes);
     std::snprintf(ctx->last_plan, sizeof ctx->last_plan,
-                  "mapping=%d rows_per_lane=%d splits=%d split_len=%lld prec=%s%s", p.mapping,
+                  "mapping=%d rows_per_lane=%d splits=%d split_len=%lld prec=%s%s%s", p.mapping,
                   p.rows_per_lane, p.splits, (long long)split_len, mixed ? "mixed" : "fp64",
+                  p.f64 && prec == NB_MIXED ? " requested=mixed" : "",
                   fixed ? " workspace=fixed" : "");
 
     // timing events are created on demand, so the allocation-free path is

@@ -108,12 +108,14 @@ __global__ __launch_bounds__(kBlock) void irregular_kernel(int64_t n, const doub
                          vz - vzi, mj);
         }
     }
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    az = wave_sum(az);
-    jx = wave_sum(jx);
-    jy = wave_sum(jy);
-    jz = wave_sum(jz);
+    double r[6] = {ax, ay, az, jx, jy, jz};
+    group_sums<kWave, 6>(r);
+    ax = r[0];
+    ay = r[1];
+    az = r[2];
+    jx = r[3];
+    jy = r[4];
+    jz = r[5];
     const bool nonfin = !finite6(ax, ay, az, jx, jy, jz);
     const uint64_t bb = __ballot(bad);
     if (lane == 0) {

@@ -19,7 +19,7 @@ def test_autotune_roundtrip_and_parity(tmp_path):
         nb.autotune(8192, path, force=True, ctx=ctx)
         with open(path) as f:
             lines = f.read().splitlines()
-        assert lines[0] == "nbreg-tune 1" and len(lines) > 4
+        assert lines[0] == "nbreg-tune 2" and len(lines) > 4
         say(f"autotune table: {len(lines) - 1} entries")
         # a fresh context loads the table without re-timing
         ctx2 = nb.Context(0)

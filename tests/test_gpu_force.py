@@ -402,3 +402,146 @@ def test_more_than_64_splits_per_merge_lane(ctx):
         assert host(res[2]).min() > 10
     finally:
         ctx.set_plan(0, 0, 0)
+
+
+def _same_result(got, want, cap, what):
+    """Two results of one call are the same bits (list entries past a row's
+    count are undefined and not compared)."""
+    for k, name in ((0, "acc"), (1, "jerk"), (2, "nb_count"), (4, "overflow")):
+        assert np.array_equal(got[k], want[k]), f"{name} differs: {what}"
+    check_lists(got[2], got[3], want[2], want[3], cap)
+
+
+@pytest.mark.parametrize("plan", [(0, 0, 0), (1, 1, 1), (1, 1, 6), (2, 1, 400)])
+def test_refinement_of_every_flagged_row(plan):
+    """A mixed-precision tolerance so small that every row is flagged: every
+    row is recomputed in FP64 by the refinement launch (chunk partials, added
+    by the work-group that finishes last), so the mixed call meets the FP64
+    bar.  Calls in between that flag nothing, and repeated calls, leave the
+    refinement's arrival word ready: the flagged call gives the same bits
+    every time.  Plans: automatic, one split (rows flagged by the force
+    kernel), a few splits (lane-group merge), 313 splits (work-group merge)."""
+    say(f"refinement of every row, plan {plan}")
+    c = nb.Context(0)
+    try:
+        n = 20000
+        x, v, m = _uniform_cube(911, n)
+        ib = np.random.default_rng(912).choice(n, 300, replace=False).astype(np.int32)
+        rs2 = np.full(ib.size, 0.08 ** 2)
+        cap = 256
+        X, V, M, IB, RS = dev(x), dev(v), dev(m), dev(ib), dev(rs2)
+        if plan != (0, 0, 0):
+            c.set_plan(*plan)
+        ref = oracle_rows(x, v, m, ib, rs2, cap)
+        runs = []
+        for k in range(3):
+            c.set_mixed_tolerance(1e-30, 32.0)
+            res = nb.regular_force(X, V, M, IB, RS, cap, "mixed", ctx=c)
+            assert c.last_refined_rows() == ib.size
+            compare_force(res, x, v, m, ib, rs2, cap, TOL_FP64, ref=ref)
+            runs.append([host(t) for t in res])
+            c.set_mixed_tolerance()   # the default: few rows, or none, flagged
+            res = nb.regular_force(X, V, M, IB, RS, cap, "mixed", ctx=c)
+            compare_force(res, x, v, m, ib, rs2, cap, TOL_MIXED, ref=ref)
+        for r in runs[1:]:
+            _same_result(r, runs[0], cap, "repeated flagged call")
+    finally:
+        c.close()
+
+
+def test_graph_replay_of_small_blocks(ctx):
+    """A stepping loop may capture its block calls in a graph: replays of a
+    captured small-block call (split force launch, merge and refinement, no
+    host work) reproduce the eager call bit for bit, replay after replay,
+    with eager calls and synchronisations in between."""
+    say("graph replay of small blocks")
+    n = 1 << 16
+    x, v, m = _uniform_cube(913, n)
+    X, V, M = dev(x), dev(v), dev(m)
+    rng = np.random.default_rng(914)
+    for size in (1, 32):
+        for prec in ("mixed", "fp64"):
+            IB = dev(rng.choice(n, size, replace=False).astype(np.int32))
+            RS = dev(np.full(size, 0.05 ** 2))
+            eager = [host(t) for t in nb.regular_force(X, V, M, IB, RS, 128, prec, ctx=ctx)]
+            out = tuple(torch.empty_like(torch.from_numpy(e)).cuda() for e in eager)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                nb.regular_force(X, V, M, IB, RS, 128, prec, out=out, ctx=ctx)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, capture_error_mode="thread_local"):
+                nb.regular_force(X, V, M, IB, RS, 128, prec, out=out, ctx=ctx)
+            for rep in range(3):
+                for t in out:
+                    t.fill_(-1)
+                g.replay()
+                torch.cuda.synchronize()
+                _same_result([host(t) for t in out], eager, 128, f"replay {rep}, {size} rows, {prec}")
+                again = [host(t) for t in nb.regular_force(X, V, M, IB, RS, 128, prec, ctx=ctx)]
+                _same_result(again, eager, 128, f"eager call after replay {rep}")
+            del g
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_workgroup_merge_many_rows_and_row_independence(ctx, prec):
+    """100 rows with 313 j-splits each (work-group merge, many work-groups
+    resident per CU; wave force kernel with four rows per wave, the row
+    groups of a split on consecutive waves): parity with the oracle, and each
+    row's results are the same bits as a call with that row alone under the
+    same split plan (a row's sums depend only on the row and the splits)."""
+    say(f"work-group merge of 100 rows {prec}")
+    n = 40000
+    x, v, m = _uniform_cube(915, n)
+    ib = np.random.default_rng(916).choice(n, 100, replace=False).astype(np.int32)
+    rs2 = np.random.default_rng(917).uniform(0.02, 0.12, ib.size) ** 2
+    cap = 200
+    X, V, M = dev(x), dev(v), dev(m)
+    try:
+        for plan in ((2, 4, 400), (2, 1, 400)):
+            ctx.set_plan(*plan)
+            res = nb.regular_force(X, V, M, dev(ib), dev(rs2), cap, prec, ctx=ctx)
+            assert int(ctx.last_plan().split("splits=")[1].split()[0]) == 313
+            compare_force(res, x, v, m, ib, rs2, cap, TOL[prec])
+            full = [host(t) for t in res]
+            for b in (0, 37, 99):
+                one = [host(t) for t in nb.regular_force(X, V, M, dev(ib[b:b + 1]),
+                                                          dev(rs2[b:b + 1]), cap, prec, ctx=ctx)]
+                assert np.array_equal(one[0][:, 0], full[0][:, b])
+                assert np.array_equal(one[1][:, 0], full[1][:, b])
+                assert one[2][0] == full[2][b]
+                k = min(int(full[2][b]), cap)
+                assert np.array_equal(one[3][0, :k], full[3][b, :k])
+    finally:
+        ctx.set_plan(0, 0, 0)
+
+
+def test_small_mixed_blocks_run_fp64_kernels(ctx):
+    """Under automatic plans a mixed-precision request on a block of at most
+    128 rows runs the FP64 kernels (latency-bound there) and meets the FP64
+    bar; 129 rows run the mixed kernels; a forced plan keeps them too."""
+    say("small mixed blocks on FP64 kernels")
+    n = 30000
+    x, v, m = _uniform_cube(918, n)
+    rng = np.random.default_rng(919)
+    X, V, M = dev(x), dev(v), dev(m)
+    for n_i, want in ((1, "prec=fp64 requested=mixed"), (128, "prec=fp64 requested=mixed"),
+                      (129, "prec=mixed")):
+        ib = rng.choice(n, n_i, replace=False).astype(np.int32)
+        rs2 = np.full(n_i, 0.07 ** 2)
+        res = nb.regular_force(X, V, M, dev(ib), dev(rs2), 128, "mixed", ctx=ctx)
+        assert want in ctx.last_plan(), ctx.last_plan()
+        tol = TOL_FP64 if "fp64" in want else TOL_MIXED
+        compare_force(res, x, v, m, ib, rs2, 128, tol)
+        if "fp64" in want:
+            f = nb.regular_force(X, V, M, dev(ib), dev(rs2), 128, "fp64", ctx=ctx)
+            _same_result([host(t) for t in res], [host(t) for t in f], 128, f"{n_i} rows")
+    try:
+        ctx.set_plan(2, 1, 0)
+        ib = rng.choice(n, 8, replace=False).astype(np.int32)
+        nb.regular_force(X, V, M, dev(ib), dev(np.full(8, 0.07 ** 2)), 128, "mixed", ctx=ctx)
+        assert "prec=mixed" in ctx.last_plan()
+    finally:
+        ctx.set_plan(0, 0, 0)
