@@ -327,14 +327,35 @@ __global__ __launch_bounds__(kBlock) void redo_kernel(ForceArgs a)
     __syncthreads();
     if (!last) return;
     __threadfence();   // every work-group's partials are visible from here
+    // a lane per row adds its chunk partials in chunk order; the 48-byte
+    // partials of kFinalBatch chunks are loaded before any is added
+    constexpr int kFinalBatch = 8;
     for (int32_t q = threadIdx.x; q < par; q += blockDim.x) {
         double s[6] = {0, 0, 0, 0, 0, 0};
         const int32_t nc = redo_row_chunks(a, q);
-        const double *p = a.redo_part + (int64_t)q * C * 6;
-#pragma unroll 4
-        for (int32_t c = 0; c < nc; ++c)
+        const double2 *p = reinterpret_cast<const double2 *>(a.redo_part + (int64_t)q * C * 6);
+        int32_t c = 0;
+        for (; c + kFinalBatch <= nc; c += kFinalBatch) {
+            double2 t[kFinalBatch][3];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) s[k] += p[c * 6 + k];
+            for (int u = 0; u < kFinalBatch; ++u)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) t[u][k] = p[(int64_t)(c + u) * 3 + k];
+#pragma unroll
+            for (int u = 0; u < kFinalBatch; ++u)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    s[2 * k] += t[u][k].x;
+                    s[2 * k + 1] += t[u][k].y;
+                }
+        }
+        for (; c < nc; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double2 t = p[(int64_t)c * 3 + k];
+                s[2 * k] += t.x;
+                s[2 * k + 1] += t.y;
+            }
         write_forces(a, a.redo_rows[q], s);
     }
     if (threadIdx.x == 0) *a.redo_arrive = 0;   // every work-group has arrived
