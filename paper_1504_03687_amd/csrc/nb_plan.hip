@@ -38,12 +38,14 @@ int64_t max_splits(int64_t n, int mapping)
 // Split count of the automatic plan for a given mapping and rows per lane
 // (or per wave).
 //  * mapping 2 (small blocks stream the j-set): about 2 waves per SIMD in
-//    total; more splits only add merge work (measured at N = 2^20,
-//    n_i = 1 .. 255).
+//    total, and at most kWaveMaxSplits splits per row; more splits only add
+//    merge work (measured at N = 2^20, n_i = 1 .. 255).
 //  * mapping 1: many short work-groups even out their run-time differences;
 //    a split sweep over the step-level blocks at N = 2^20 was best near 64
 //    work-groups per CU in total (full block: 4 splits, +3-4%; 52428 rows:
 //    80 splits instead of 10, +25%).
+constexpr int64_t kWaveMaxSplits = 1024;
+
 int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, int rows)
 {
     const int64_t cus = ctx->cu_count > 0 ? ctx->cu_count : 256;
@@ -62,7 +64,13 @@ int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, i
     // the count further.  Mapping 1 rounds up: at ~64 work-groups per CU one
     // extra costs little.
     const int64_t u = std::max<int64_t>(units, 1);
-    const int64_t s = mapping == 2 ? std::max<int64_t>(1, target / u) : (target + u - 1) / u;
+    int64_t s = mapping == 2 ? std::max<int64_t>(1, target / u) : (target + u - 1) / u;
+    // mapping 2 with few row groups: at most kWaveMaxSplits splits.  Each
+    // split adds a partial to every row's merge, which one work-group reads;
+    // with bodies loaded four iterations ahead, one wave per SIMD streams the
+    // j-set as fast as two.  FP64, N = 2^20, forced plans: 1 row 20.6 us at
+    // 2048 splits, 19.7 at 1024, 21.1 at 512; 4 rows 29.1 / 25.6 / 31.9 us.
+    if (mapping == 2) s = std::min(s, kWaveMaxSplits);
     return std::max<int64_t>(1, std::min(s, max_splits(n, mapping)));
 }
 
