@@ -74,18 +74,54 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
     const int64_t j1 = j0 + a.split_len < a.n ? j0 + a.split_len : a.n;
     const Dest d{a.splits == 1, (int64_t)split, 0, (int64_t)a.splits};
 
-    // Row data is uniform across the wave (scalar loads, scalar registers).
+    // Row data is uniform across the wave (scalar registers).  The loads of
+    // all G rows are issued together, at in-range indices, and invalid rows
+    // are masked afterwards: every wave starts at the same time, so the
+    // round trips of this setup add directly to the launch (with a branch per
+    // row the G rows took 2 G dependent round trips).
     double rx[G], ry[G], rz[G], rvx[G], rvy[G], rvz[G], hi[G];
     float rs2f[G], candf[G];
     int32_t ri[G], cnt[G], lcap[G];
     int32_t *lst[G];
     Sums<MIXED> S[G];
+    int64_t iraw[G];
+    double rsv[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int64_t b = group * G + g;
+        const int64_t bc = b < a.n_i ? b : a.n_i - 1;
+        iraw[g] = a.i_block[bc];
+        rsv[g] = a.rs2[bc];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int64_t b = group * G + g;
+        const bool ok = b < a.n_i && iraw[g] >= 0 && iraw[g] < a.n;
+        const int64_t i = ok ? iraw[g] : 0;
         S[g].zero();
         cnt[g] = 0;
-        ri[g] = -1;
+        ri[g] = ok ? (int32_t)i : -1;
+        rx[g] = a.xp[i];
+        ry[g] = a.xp[a.n + i];
+        rz[g] = a.xp[2 * a.n + i];
+        rvx[g] = a.vp[i];
+        rvy[g] = a.vp[a.n + i];
+        rvz[g] = a.vp[2 * a.n + i];
+        rs2f[g] = (float)rsv[g];
+        hi[g] = cand_bound_f64(rs2f[g]);
+        candf[g] = cand_bound_f32(rs2f[g], a.near_factor);
+        if (d.direct) {
+            lst[g] = a.nb_list + b * (int64_t)a.cap;
+            lcap[g] = a.cap;
+        } else {
+            lst[g] = a.seg_list + dest_slot(d, b) * kSegCap;
+            lcap[g] = kSegCap;
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (ri[g] >= 0) continue;
+        // no row (past n_i, or a bad index): far away, never a neighbour
         rx[g] = ry[g] = rz[g] = kFar * 0.5;
         rvx[g] = rvy[g] = rvz[g] = 0.0;
         rs2f[g] = -1.0f;
@@ -93,28 +129,6 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
         candf[g] = -1.0f;
         lst[g] = nullptr;
         lcap[g] = 0;
-        if (b < a.n_i) {
-            const int64_t i = a.i_block[b];
-            if (i >= 0 && i < a.n) {
-                ri[g] = (int32_t)i;
-                rx[g] = a.xp[i];
-                ry[g] = a.xp[a.n + i];
-                rz[g] = a.xp[2 * a.n + i];
-                rvx[g] = a.vp[i];
-                rvy[g] = a.vp[a.n + i];
-                rvz[g] = a.vp[2 * a.n + i];
-                rs2f[g] = (float)a.rs2[b];
-                hi[g] = cand_bound_f64(rs2f[g]);
-                candf[g] = cand_bound_f32(rs2f[g], a.near_factor);
-                if (d.direct) {
-                    lst[g] = a.nb_list + b * (int64_t)a.cap;
-                    lcap[g] = a.cap;
-                } else {
-                    lst[g] = a.seg_list + dest_slot(d, b) * kSegCap;
-                    lcap[g] = kSegCap;
-                }
-            }
-        }
     }
 
     // the bodies of the next D iterations are loaded ahead (a ring of D
