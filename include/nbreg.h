@@ -96,11 +96,14 @@ const char *nb_error_string(int code);
 int nb_version(void);
 
 /* Plan override used by tests and the autotuner: 0 in a field means "choose
- * automatically".  mapping: 1 = one row per lane with j-tiles in LDS,
- * 2 = one row per wavefront with j spread over lanes (small blocks).
- * rows_per_lane: 1, 2 or 4 (mapping 1).  splits: number of contiguous j
- * ranges whose partial sums are combined in FP64 (>= 1).  The override holds
- * until changed; pass all zeros to go back to automatic plans. */
+ * automatically".  mapping: 1 = one row per lane with j-tiles in LDS
+ * (256-lane work-groups), 2 = 1, 2 or 4 rows per wavefront with j spread
+ * over lanes (the smallest blocks), 3 = one row per lane in one-wave
+ * work-groups with 64-body LDS tiles (blocks of a few dozen to a few hundred
+ * rows).  rows_per_lane: 1, 2 or 4 (mapping 1; rows per wave for mapping 2;
+ * ignored by mapping 3).  splits: number of contiguous j ranges whose partial
+ * sums are combined in FP64 (>= 1).  The override holds until changed; pass
+ * all zeros to go back to automatic plans. */
 int nb_ctx_set_plan(nb_ctx *ctx, int mapping, int rows_per_lane, int splits);
 /* Describes the plan of the last nb_regular_force call into buf (text). */
 int nb_ctx_last_plan(nb_ctx *ctx, char *buf, int len);
@@ -161,7 +164,7 @@ int nb_predict(nb_ctx *ctx, int64_t n, double t, const double *x, const double *
  * running sums, with FP64 cross-split reduction; pairs closer than two
  * neighbour radii are evaluated in FP64, and rows whose rounding-error
  * estimate is too large are recomputed in FP64 (nb_ctx_set_mixed_tolerance).
- * Small blocks (n_i <= 128 under automatic plans) are latency-bound, and an
+ * Small blocks (n_i <= 40 under automatic plans) are latency-bound, and an
  * NB_MIXED request on them runs the FP64 kernels instead: no slower there,
  * no refinement, and results to the FP64 bar (nb_ctx_last_plan then reads
  * "prec=fp64 requested=mixed"; a plan set by nb_ctx_set_plan keeps the

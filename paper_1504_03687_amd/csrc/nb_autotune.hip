@@ -75,7 +75,7 @@ static int load_table(nb_ctx *ctx, const char *path, int64_t n_bucket, bool *fou
     long long nb, nib;
     while (std::fscanf(f, "%d %lld %lld %d %d %d %d", &prec, &nb, &nib, &mapping, &rows, &splits,
                        &f64) == 7) {
-        if (mapping < 1 || mapping > 2 || splits < 1 ||
+        if (mapping < 1 || mapping > 3 || splits < 1 ||
             !(rows == 1 || rows == 2 || rows == 4) || f64 < 0 || f64 > 1)
             continue;
         ctx->tuned[std::make_tuple(prec, (int64_t)nb, (int64_t)nib)] =
@@ -152,12 +152,14 @@ extern "C" int nb_autotune(nb_ctx *ctx, int64_t n, const char *cache_path, int f
             // candidates around the automatic plan of each mapping
             ctx->has_forced = false;
             std::vector<nb::Plan> cands;
-            for (int mapping = 1; mapping <= 2; ++mapping) {
+            for (int mapping = 1; mapping <= 3; ++mapping) {
                 if (mapping == 1 && ni < 64) continue;
+                if (mapping == 3 && (ni < 16 || ni > 1024)) continue;
                 const int rows_opts[3] = {1, 2, 4};
                 for (int rows : rows_opts) {
                     if (mapping == 1 && rows == 4) continue;
                     if (mapping == 2 && rows > ni) continue;
+                    if (mapping == 3 && rows != 1) continue;
                     // the automatic split count of this mapping, halved and doubled
                     const int64_t base = default_splits(ctx, n, ni, mapping, rows);
                     for (int64_t sc : {base / 2, base, base * 2}) {

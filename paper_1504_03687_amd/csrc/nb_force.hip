@@ -55,6 +55,22 @@ __global__ __launch_bounds__(kBlock) void force_rows_kernel(ForceArgs a)
                          a.near_factor);
 }
 
+// One-wave work-groups of the row-per-lane pass (64 rows, a 64-body LDS tile):
+// blocks of a few row tiles fill the lanes of 64-row groups instead of
+// leaving most of a 256-lane work-group idle.  grid = (ceil(n_i / 64), splits).
+template <bool MIXED>
+__global__ __launch_bounds__(kWave) void force_rows_wave_kernel(ForceArgs a)
+{
+    __shared__ JBody tile[2][kWave];
+    clear_call_words(a);
+    const int32_t split = blockIdx.y;
+    const int64_t j0 = (int64_t)split * a.split_len;
+    const int64_t j1 = j0 + a.split_len < a.n ? j0 + a.split_len : a.n;
+    const Dest d{a.splits == 1, (int64_t)split, 0, (int64_t)a.splits};
+    rows_pass<MIXED, 1, kWave, kWave>(a, tile, (int64_t)blockIdx.x * kWave, a.n_i, j0, j1, d,
+                                      a.near_factor);
+}
+
 // Wave w (global) handles row group w % ngroups (rows G*(w%ngroups) + g) over
 // j-range w / ngroups.  The row groups of one j-range are consecutive waves,
 // mostly of one work-group, so the groups after the first read that range
@@ -496,6 +512,9 @@ static hipError_t launch_force_t(const Plan &p, const ForceArgs &a, hipStream_t 
         case 4: hipLaunchKernelGGL((force_rows_kernel<MIXED, 4>), grid, dim3(kBlock), 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
+    } else if (p.mapping == 3) {
+        dim3 grid((unsigned)((a.n_i + kWave - 1) / kWave), (unsigned)p.splits);
+        hipLaunchKernelGGL((force_rows_wave_kernel<MIXED>), grid, dim3(kWave), 0, s, a);
     } else {
         const int G = p.rows_per_lane;
         const int64_t waves = ((a.n_i + G - 1) / G) * (int64_t)p.splits;

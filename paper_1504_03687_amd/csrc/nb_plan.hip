@@ -31,7 +31,7 @@ int64_t bucket_log2(int64_t v)
 // 362 us): 2048 work-groups spread evenly over 256 CUs.
 int64_t max_splits(int64_t n, int mapping)
 {
-    const int64_t unit = mapping == 2 ? 4 * nb::kWave : 2 * nb::kTile;
+    const int64_t unit = mapping == 2 ? 4 * nb::kWave : mapping == 3 ? 2 * nb::kWave : 2 * nb::kTile;
     return std::max<int64_t>(1, (n + unit - 1) / unit);
 }
 
@@ -40,6 +40,9 @@ int64_t max_splits(int64_t n, int mapping)
 //  * mapping 2 (small blocks stream the j-set): about 2 waves per SIMD in
 //    total, and at most kWaveMaxSplits splits per row; more splits only add
 //    merge work (measured at N = 2^20, n_i = 1 .. 255).
+//  * mapping 3 (one-wave work-groups, 64 rows each): about 16 work-groups
+//    per CU in total (a 64-row block at N = 2^20: 4096 splits 104.7 us,
+//    2048 108.4, 1024 149.9, FP64).
 //  * mapping 1: many short work-groups even out their run-time differences;
 //    a split sweep over the step-level blocks at N = 2^20 was best near 64
 //    work-groups per CU in total (full block: 4 splits, +3-4%; 52428 rows:
@@ -53,6 +56,9 @@ int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, i
     if (mapping == 2) {
         units = (n_i + rows - 1) / rows;                       // row groups, one wave each
         target = cus * 8;
+    } else if (mapping == 3) {
+        units = (n_i + nb::kWave - 1) / nb::kWave;             // one-wave work-groups
+        target = cus * 16;
     } else {
         units = (n_i + (int64_t)rows * nb::kBlock - 1) / ((int64_t)rows * nb::kBlock);
         target = cus * 64;                                      // work-groups
@@ -74,27 +80,33 @@ int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, i
     return std::max<int64_t>(1, std::min(s, max_splits(n, mapping)));
 }
 
-// Largest block that takes the wave mapping in the automatic plan.  Above it
-// the row-per-lane kernel is faster even with most lanes of its single row
-// tile idle.  Measured at N = 2^20 (steady state): mixed 128 rows 253 us
-// (wave) vs 259 us, 160 rows 326 vs 277 us; FP64 160 rows 290 vs 342 us,
-// 192 rows 340 vs 344 us, 255 rows 430 vs 375 us.
-constexpr int32_t kWaveMaxRowsMixed = 128;
-constexpr int32_t kWaveMaxRowsF64 = 192;
+// Mappings of the automatic plan by block size, from steady-state calls at
+// N = 2^20 (mixed / FP64 kernels, whole call):
+//  * wave mapping (rows in scalar registers, lanes over j) up to
+//    kWaveMaxRows: 32 rows 67.6 us FP64, against 104.7 us with one-wave
+//    row-per-lane work-groups (half their lanes idle) and more than that with
+//    256-lane work-groups;
+//  * one-wave row-per-lane work-groups (mapping 3) up to kRowsWaveMaxRows:
+//    64 rows 95 / 110 us against 136 (wave), 128 rows 154 / 192 us against
+//    236, 192 rows 214 / 274 us against 232 (256-lane) / 338 (wave);
+//  * 256-lane row-per-lane work-groups above: 256 rows 302 / 349 us against
+//    319 / 355 with one-wave work-groups.
+constexpr int32_t kWaveMaxRows = 40;
+constexpr int32_t kRowsWaveMaxRows = 192;
 
 // Largest block whose mixed-precision request runs the FP64 kernels in the
-// automatic plan.  Small blocks are bound by memory latency, not arithmetic,
-// so the FP64 wave kernel is no slower than the mixed one, and it needs no
-// refinement launch (nor, for a flagged row, the refinement itself).  Whole
-// call, N = 2^20 (steady state), mixed vs FP64 kernels: 1 row 22.7 vs 20.4
-// us, 8 rows 36.7 vs 31.4, 32 rows 124.7 (one row refined) vs 67.3, 64 rows
-// 155 vs 137, 128 rows 270 vs 238; at 192 rows the mixed row-per-lane kernel
-// is ahead (232 vs 338 us).  The results then meet the FP64 bar.
-constexpr int32_t kMixedAsF64MaxRows = 128;
+// automatic plan: the wave mapping, which is bound by memory latency, so its
+// FP64 kernel is no slower than the mixed one, and it needs no refinement
+// launch (nor, for a flagged row, the refinement itself).  N = 2^20, mixed vs
+// FP64 wave kernels: 1 row 22.7 vs 20.4 us, 8 rows 36.7 vs 31.4, 32 rows
+// 124.7 (one row refined) vs 67.3.  From 64 rows up the mixed one-wave
+// row-per-lane kernel is ahead (95 against the FP64 wave kernel's 137 us).
+// The results of such a call meet the FP64 bar.
+constexpr int32_t kMixedAsF64MaxRows = kWaveMaxRows;
 
 // Automatic plan for a block of n_i rows against n bodies: the autotuned
-// entry for the size buckets if there is one, else the wave mapping for
-// small blocks and one row per lane above.
+// entry for the size buckets if there is one, else the mapping for its size
+// (above).
 Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed)
 {
     auto it = ctx->tuned.find(std::make_tuple((int)mixed, bucket_log2(n), bucket_log2(n_i)));
@@ -105,12 +117,14 @@ Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed)
         return p;
     }
     Plan p{};
-    if (n_i <= (mixed ? kWaveMaxRowsMixed : kWaveMaxRowsF64)) {
+    p.rows_per_lane = 1;
+    if (n_i <= kWaveMaxRows) {
         p.mapping = 2;
         p.rows_per_lane = n_i >= 4 ? 4 : (n_i >= 2 ? 2 : 1);
+    } else if (n_i <= kRowsWaveMaxRows) {
+        p.mapping = 3;
     } else {
         p.mapping = 1;
-        p.rows_per_lane = 1;
     }
     p.splits = (int)default_splits(ctx, n, n_i, p.mapping, p.rows_per_lane);
     return p;

@@ -241,7 +241,7 @@ int nb_ctx_destroy(nb_ctx *ctx)
 int nb_ctx_set_plan(nb_ctx *ctx, int mapping, int rows_per_lane, int splits)
 {
     if (!ctx) return NB_ERR_INVALID_ARG;
-    if (mapping < 0 || mapping > 2 || splits < 0) return NB_ERR_INVALID_ARG;
+    if (mapping < 0 || mapping > 3 || splits < 0) return NB_ERR_INVALID_ARG;
     if (!(rows_per_lane == 0 || rows_per_lane == 1 || rows_per_lane == 2 || rows_per_lane == 4))
         return NB_ERR_INVALID_ARG;
     ctx->forced = Plan{mapping, rows_per_lane, splits};

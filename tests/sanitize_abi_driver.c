@@ -38,7 +38,8 @@ int main(void)
 
     /* context settings */
     EXPECT(nb_ctx_set_stream(ctx, NULL), NB_OK);
-    EXPECT(nb_ctx_set_plan(ctx, 3, 0, 0), E);
+    EXPECT(nb_ctx_set_plan(ctx, 4, 0, 0), E);
+    EXPECT(nb_ctx_set_plan(ctx, 3, 0, 0), NB_OK);
     EXPECT(nb_ctx_set_plan(ctx, 1, 3, 0), E);
     EXPECT(nb_ctx_set_plan(ctx, 1, 1, -2), E);
     EXPECT(nb_ctx_set_plan(ctx, 2, 4, 16), NB_OK);

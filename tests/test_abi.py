@@ -69,7 +69,8 @@ def test_argument_validation(host_ctx):
     assert pr(n=0) == E and pr(m=p(8)) == E and pr(t=float("nan")) == E
     assert pr() == -4 and pr(m=p(8), m32=p(9)) == -4
     # plan override
-    assert L.nb_ctx_set_plan(host_ctx, 3, 0, 0) == E
+    assert L.nb_ctx_set_plan(host_ctx, 4, 0, 0) == E
+    assert L.nb_ctx_set_plan(host_ctx, 3, 0, 0) == 0
     assert L.nb_ctx_set_plan(host_ctx, 1, 3, 0) == E
     assert L.nb_ctx_set_plan(host_ctx, 1, 2, 4) == 0
     assert L.nb_ctx_set_plan(host_ctx, 0, 0, 0) == 0

@@ -67,7 +67,8 @@ def test_plummer_n1024_all_active(ctx, prec):
 
 
 PLANS = [(1, 1, 1), (1, 2, 1), (1, 4, 1), (1, 1, 3), (1, 2, 5), (1, 4, 2),
-         (2, 1, 1), (2, 2, 4), (2, 4, 7), (2, 4, 1), (2, 1, 13)]
+         (2, 1, 1), (2, 2, 4), (2, 4, 7), (2, 4, 1), (2, 1, 13), (3, 1, 1), (3, 1, 5),
+         (3, 1, 40)]
 
 
 def _ragged_case(seed=31, n=3001, n_i=777):
@@ -520,19 +521,22 @@ def test_workgroup_merge_many_rows_and_row_independence(ctx, prec):
 
 def test_small_mixed_blocks_run_fp64_kernels(ctx):
     """Under automatic plans a mixed-precision request on a block of at most
-    128 rows runs the FP64 kernels (latency-bound there) and meets the FP64
-    bar; 129 rows run the mixed kernels; a forced plan keeps them too."""
+    40 rows runs the FP64 kernels (latency-bound there) and meets the FP64
+    bar; 41 and 128 rows run the mixed kernels (one-wave row-per-lane
+    work-groups); a forced plan keeps the mixed kernels too."""
     say("small mixed blocks on FP64 kernels")
     n = 30000
     x, v, m = _uniform_cube(918, n)
     rng = np.random.default_rng(919)
     X, V, M = dev(x), dev(v), dev(m)
-    for n_i, want in ((1, "prec=fp64 requested=mixed"), (128, "prec=fp64 requested=mixed"),
-                      (129, "prec=mixed")):
+    for n_i, want in ((1, "prec=fp64 requested=mixed"), (40, "prec=fp64 requested=mixed"),
+                      (41, "mapping=3 rows_per_lane=1"), (128, "mapping=3 rows_per_lane=1"),
+                      (193, "mapping=1 rows_per_lane=1")):
         ib = rng.choice(n, n_i, replace=False).astype(np.int32)
         rs2 = np.full(n_i, 0.07 ** 2)
         res = nb.regular_force(X, V, M, dev(ib), dev(rs2), 128, "mixed", ctx=ctx)
         assert want in ctx.last_plan(), ctx.last_plan()
+        assert ("fp64" in want) == ("prec=fp64" in ctx.last_plan())
         tol = TOL_FP64 if "fp64" in want else TOL_MIXED
         compare_force(res, x, v, m, ib, rs2, 128, tol)
         if "fp64" in want:
