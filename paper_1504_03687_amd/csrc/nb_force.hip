@@ -164,48 +164,80 @@ __global__ __launch_bounds__(kBlock) void force_wave_kernel(ForceArgs a)
         const JBody J = Jq[u];
         if (base + D * kWave < j1) load_body(Jq[u], a, j + D * kWave, j1);
         const int32_t jidx = (int32_t)j;
+        // differences and the candidate test of every row first, then one
+        // branch for the rare cases of all rows (one exec-mask change per
+        // iteration instead of one per row); operands and sums unchanged
+        double dx[G], dy[G], dz[G];
+        bool cand[G];
+        bool any = false;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const double dx = J.x - rx[g], dy = J.y - ry[g], dz = J.z - rz[g];
-            if constexpr (MIXED) {
-                const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-                const float r2f = __builtin_fmaf(fz, fz, __builtin_fmaf(fy, fy, fx * fx));
-                const bool cand = r2f < candf[g];
-                if (__ballot(cand)) {   // neighbours, self, near pairs (FP64 terms)
-                    // lanes past j1 hold padding (mass 0): never a neighbour
-                    const bool self = cand && jidx == ri[g];
-                    const bool nbr = cand && (r2f < rs2f[g]) && !self && j < j1;
-                    const uint64_t nm = __ballot(nbr);
-                    if (nbr) {
-                        const int p = cnt[g] + lanes_below(nm);
-                        if (p < lcap[g]) lst[g][p] = jidx;
-                    }
-                    cnt[g] += __popcll(nm);
-                    if (cand && !nbr && !self)
-                        add_term_f64(S[g].ax, S[g].ay, S[g].az, S[g].jx, S[g].jy, S[g].jz, dx,
-                                     dy, dz, J.vx - rvx[g], J.vy - rvy[g], J.vz - rvz[g], J.m);
-                }
-                accum_mixed(S[g], fx, fy, fz, r2f, J.vx - rvx[g], J.vy - rvy[g], J.vz - rvz[g],
-                            J.m32, cand);
-            } else {
-                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                const bool cand = r2 < hi[g];
-                bool excl = false;
-                if (__ballot(cand)) {
-                    const bool self = cand && jidx == ri[g];
-                    const bool nbr =
-                        cand && (canon_r2f(dx, dy, dz) < rs2f[g]) && !self && j < j1;
-                    const uint64_t nm = __ballot(nbr);
-                    if (nbr) {
-                        const int p = cnt[g] + lanes_below(nm);
-                        if (p < lcap[g]) lst[g][p] = jidx;
-                    }
-                    cnt[g] += __popcll(nm);
-                    excl = nbr || self;
-                }
-                accum_f64(S[g], dx, dy, dz, r2, J.vx - rvx[g], J.vy - rvy[g], J.vz - rvz[g],
-                          J.m, excl);
+            dx[g] = J.x - rx[g];
+            dy[g] = J.y - ry[g];
+            dz[g] = J.z - rz[g];
+        }
+        if constexpr (MIXED) {
+            float fx[G], fy[G], fz[G], r2f[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                fx[g] = (float)dx[g];
+                fy[g] = (float)dy[g];
+                fz[g] = (float)dz[g];
+                r2f[g] = __builtin_fmaf(fz[g], fz[g], __builtin_fmaf(fy[g], fy[g], fx[g] * fx[g]));
+                cand[g] = r2f[g] < candf[g];
+                any = any || cand[g];
             }
+            if (__ballot(any)) {   // neighbours, self, near pairs (FP64 terms)
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    // lanes past j1 hold padding (mass 0): never a neighbour
+                    const bool self = cand[g] && jidx == ri[g];
+                    const bool nbr = cand[g] && (r2f[g] < rs2f[g]) && !self && j < j1;
+                    const uint64_t nm = __ballot(nbr);
+                    if (nbr) {
+                        const int p = cnt[g] + lanes_below(nm);
+                        if (p < lcap[g]) lst[g][p] = jidx;
+                    }
+                    cnt[g] += __popcll(nm);
+                    if (cand[g] && !nbr && !self)
+                        add_term_f64(S[g].ax, S[g].ay, S[g].az, S[g].jx, S[g].jy, S[g].jz,
+                                     dx[g], dy[g], dz[g], J.vx - rvx[g], J.vy - rvy[g],
+                                     J.vz - rvz[g], J.m);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                accum_mixed(S[g], fx[g], fy[g], fz[g], r2f[g], J.vx - rvx[g], J.vy - rvy[g],
+                            J.vz - rvz[g], J.m32, cand[g]);
+        } else {
+            double r2[G];
+            bool excl[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                r2[g] = __builtin_fma(dz[g], dz[g], __builtin_fma(dy[g], dy[g], dx[g] * dx[g]));
+                cand[g] = r2[g] < hi[g];
+                excl[g] = false;
+                any = any || cand[g];
+            }
+            if (__ballot(any)) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const bool self = cand[g] && jidx == ri[g];
+                    const bool nbr = cand[g] && (canon_r2f(dx[g], dy[g], dz[g]) < rs2f[g]) &&
+                                     !self && j < j1;
+                    const uint64_t nm = __ballot(nbr);
+                    if (nbr) {
+                        const int p = cnt[g] + lanes_below(nm);
+                        if (p < lcap[g]) lst[g][p] = jidx;
+                    }
+                    cnt[g] += __popcll(nm);
+                    excl[g] = nbr || self;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                accum_f64(S[g], dx[g], dy[g], dz[g], r2[g], J.vx - rvx[g], J.vy - rvy[g],
+                          J.vz - rvz[g], J.m, excl[g]);
         }
         if constexpr (MIXED) {
             if (++iter == kFold) {
