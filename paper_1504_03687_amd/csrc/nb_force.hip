@@ -319,16 +319,50 @@ __device__ __forceinline__ void write_forces(const ForceArgs &a, int64_t b, cons
     a.jerk[2 * (int64_t)a.n_i + b] = v[5];
 }
 
-// Refinement of the listed rows in one launch.  Pass 1: the first redo_rcap
-// listed rows as (row group, chunk) items over the whole grid (chunk partials
-// to scratch); any further rows one work-group each, chunks in order.  Pass 2:
-// the work-group that finishes pass 1 last adds each buffered row's chunk
-// partials in chunk order and overwrites its forces.  Both routes give the
-// same chunk-ordered sum.  A group is kRedoRows consecutive listed rows: when
-// they share one j-range (always in a single-block call) they are summed
-// together, each body loaded once; otherwise row by row.  Chunks past a row's
-// own range are skipped.  With no listed row every work-group leaves at once
-// (no fence, no atomic), which is the common case of small blocks.
+// Final sums of the buffered rows: six lanes per row, a lane per force
+// component, each adding the row's chunk partials of its component in chunk
+// order (kFinalBatch of them loaded before any is added).  Starting from zero
+// in chunk order, this is the sum of the unbuffered route.  slot / slots: this
+// lane's row slot and the number of slots (rows q = slot, slot + slots, ...).
+constexpr int kFinalBatch = 16;
+constexpr int kFinalRowsPerGroup = kBlock / 6;
+
+__device__ __forceinline__ void redo_final_rows(const ForceArgs &a, int32_t par, int32_t slot,
+                                                int32_t slots)
+{
+    const int k = (int)(threadIdx.x % 6);
+    if (threadIdx.x >= kFinalRowsPerGroup * 6) return;
+    for (int32_t q = slot; q < par; q += slots) {
+        const int32_t nc = redo_row_chunks(a, q);
+        const int64_t row = a.redo_rows[q];
+        const double *p = a.redo_part + (int64_t)q * a.redo_chunks * 6 + k;
+        double s = 0.0;
+        for (int32_t c0 = 0; c0 < nc; c0 += kFinalBatch) {
+            double t[kFinalBatch];
+#pragma unroll
+            for (int u = 0; u < kFinalBatch; ++u) t[u] = c0 + u < nc ? p[(int64_t)(c0 + u) * 6] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kFinalBatch; ++u)
+                if (c0 + u < nc) s += t[u];
+        }
+        double *dst = k < 3 ? a.acc + (int64_t)k * a.n_i : a.jerk + (int64_t)(k - 3) * a.n_i;
+        dst[row] = s;
+    }
+}
+
+// Refinement of the listed rows.  Pass 1: the first redo_rcap listed rows as
+// (row group, chunk) items over the whole grid (chunk partials to scratch);
+// any further rows one work-group each, chunks in order.  Pass 2 adds each
+// buffered row's chunk partials in chunk order and overwrites its forces:
+// with FUSED, the work-group that finishes pass 1 last does it (one launch,
+// for calls that can list few rows); otherwise redo_final_kernel, launched
+// next, spreads it over the GPU.  Both routes give the same chunk-ordered
+// sum.  A group is kRedoRows consecutive listed rows: when they share one
+// j-range (always in a single-block call) they are summed together, each body
+// loaded once; otherwise row by row.  Chunks past a row's own range are
+// skipped.  With no listed row every work-group leaves at once (no fence, no
+// atomic), which is the common case of small blocks.
+template <bool FUSED>
 __global__ __launch_bounds__(kBlock) void redo_kernel(ForceArgs a)
 {
     __shared__ double lds[kRedoRows * 6][kBlock / kWave];
@@ -377,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void redo_kernel(ForceArgs a)
         }
         if (threadIdx.x == 0) write_forces(a, a.redo_rows[q], acc);
     }
-    if (par == 0) return;   // nothing buffered (uniform over the grid)
+    if (!FUSED || par == 0) return;   // par == 0: nothing buffered (uniform over the grid)
 
     // arrival: the chunk partials were written by lane 0, which publishes
     // them device-wide before it counts this work-group in
@@ -389,38 +423,19 @@ __global__ __launch_bounds__(kBlock) void redo_kernel(ForceArgs a)
     __syncthreads();
     if (!last) return;
     __threadfence();   // every work-group's partials are visible from here
-    // a lane per row adds its chunk partials in chunk order; the 48-byte
-    // partials of kFinalBatch chunks are loaded before any is added
-    constexpr int kFinalBatch = 8;
-    for (int32_t q = threadIdx.x; q < par; q += blockDim.x) {
-        double s[6] = {0, 0, 0, 0, 0, 0};
-        const int32_t nc = redo_row_chunks(a, q);
-        const double2 *p = reinterpret_cast<const double2 *>(a.redo_part + (int64_t)q * C * 6);
-        int32_t c = 0;
-        for (; c + kFinalBatch <= nc; c += kFinalBatch) {
-            double2 t[kFinalBatch][3];
-#pragma unroll
-            for (int u = 0; u < kFinalBatch; ++u)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) t[u][k] = p[(int64_t)(c + u) * 3 + k];
-#pragma unroll
-            for (int u = 0; u < kFinalBatch; ++u)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    s[2 * k] += t[u][k].x;
-                    s[2 * k + 1] += t[u][k].y;
-                }
-        }
-        for (; c < nc; ++c)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double2 t = p[(int64_t)c * 3 + k];
-                s[2 * k] += t.x;
-                s[2 * k + 1] += t.y;
-            }
-        write_forces(a, a.redo_rows[q], s);
-    }
     if (threadIdx.x == 0) *a.redo_arrive = 0;   // every work-group has arrived
+    redo_final_rows(a, par, (int32_t)(threadIdx.x / 6), kFinalRowsPerGroup);
+}
+
+// Pass 2 of the refinement as a launch of its own, spread over the grid: for
+// calls that can list many rows, where one work-group adding them all would
+// take longer than the rest of the refinement.
+__global__ __launch_bounds__(kBlock) void redo_final_kernel(ForceArgs a)
+{
+    const int32_t count = load_word_uniform(a.redo_count);
+    const int32_t par = count < a.redo_rcap ? count : a.redo_rcap;
+    redo_final_rows(a, par, (int32_t)(blockIdx.x * kFinalRowsPerGroup + threadIdx.x / 6),
+                    (int32_t)(gridDim.x * kFinalRowsPerGroup));
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int32_t value, int64_t count)
@@ -450,6 +465,13 @@ size_t slot_scratch_bytes(int64_t slots)
     return round256(s * kSlotComp * sizeof(double)) + round256(s * sizeof(int32_t)) +
            round256(s * kSegCap * sizeof(int32_t));
 }
+
+// Calls that can buffer at most this many refined rows add them up in the
+// work-group that finishes pass 1 last (42 rows at a time); larger ones
+// launch redo_final_kernel.  The 256-cluster ensemble
+// (about 1.2e4 buffered rows) took 0.25 ms longer per call with one
+// work-group adding them all.
+constexpr int64_t kFusedRedoRows = 1024;
 
 int32_t redo_groups_for(int cu_count) { return (cu_count > 0 ? cu_count : 256) * 4; }
 
@@ -500,7 +522,15 @@ hipError_t launch_redo(const ForceArgs &a, hipStream_t s)
     const int64_t par = std::min<int64_t>(rows, a.redo_rcap);
     const int64_t items = (par + kRedoRows - 1) / kRedoRows * a.redo_chunks + (rows - par);
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(a.redo_groups, items));
-    hipLaunchKernelGGL(redo_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, a);
+    if (par <= kFusedRedoRows) {
+        hipLaunchKernelGGL(redo_kernel<true>, dim3((unsigned)grid), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(redo_kernel<false>, dim3((unsigned)grid), dim3(kBlock), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t fgrid = std::min<int64_t>(a.redo_groups, (par + kFinalRowsPerGroup - 1) / kFinalRowsPerGroup);
+    hipLaunchKernelGGL(redo_final_kernel, dim3((unsigned)fgrid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -397,6 +397,13 @@ __device__ __forceinline__ int32_t load_word_uniform(const int32_t *p)
     return *(const __attribute__((address_space(4))) int32_t *)p;
 }
 
+// The same for a double that no lane writes during the kernel (an input, or
+// data of an earlier kernel): it lands in scalar registers.
+__device__ __forceinline__ double load_f64_uniform(const double *p)
+{
+    return *(const __attribute__((address_space(4))) double *)p;
+}
+
 // Lanes per row of the single-wave merge for a given split count: the next of
 // 4, 16, 64 at or above it.  For S <= W each lane holds at most one partial
 // and the lanes past S hold exact zeros, which the butterfly adds before any
@@ -556,14 +563,17 @@ __device__ __forceinline__ int32_t redo_row_chunks(const ForceArgs &a, int32_t q
 __device__ __forceinline__ void redo_chunk(const ForceArgs &a, int32_t q, int32_t c,
                                           double (*lds)[kBlock / kWave], double (&out)[6])
 {
-    const int64_t b = a.redo_rows[q];
-    const int64_t j0 = a.redo_j0[q], j1 = a.redo_j1[q];
+    // q is uniform: the row's data go to scalar registers
+    const int64_t b = load_word_uniform(a.redo_rows + q);
+    const int64_t j0 = load_word_uniform(a.redo_j0 + q), j1 = load_word_uniform(a.redo_j1 + q);
     const int64_t cj0 = j0 + (int64_t)c * kRedoChunk;
     const int64_t cj1 = cj0 + kRedoChunk < j1 ? cj0 + kRedoChunk : j1;
-    const int64_t i = a.i_block[b];
-    const double xi = a.xp[i], yi = a.xp[a.n + i], zi = a.xp[2 * a.n + i];
-    const double vxi = a.vp[i], vyi = a.vp[a.n + i], vzi = a.vp[2 * a.n + i];
-    const float rs2f = (float)a.rs2[b];
+    const int64_t i = load_word_uniform(a.i_block + b);
+    const double xi = load_f64_uniform(a.xp + i), yi = load_f64_uniform(a.xp + a.n + i),
+                 zi = load_f64_uniform(a.xp + 2 * a.n + i);
+    const double vxi = load_f64_uniform(a.vp + i), vyi = load_f64_uniform(a.vp + a.n + i),
+                 vzi = load_f64_uniform(a.vp + 2 * a.n + i);
+    const float rs2f = (float)load_f64_uniform(a.rs2 + b);
     const double hi = cand_bound_f64(rs2f);
     Sums<false> S;
     S.zero();
@@ -601,7 +611,7 @@ __device__ __forceinline__ void redo_chunk_rows(const ForceArgs &a, int32_t q0, 
                                                double (*lds)[kBlock / kWave],
                                                double (&out)[kRedoRows * 6])
 {
-    const int64_t j0 = a.redo_j0[q0], j1 = a.redo_j1[q0];
+    const int64_t j0 = load_word_uniform(a.redo_j0 + q0), j1 = load_word_uniform(a.redo_j1 + q0);
     const int64_t cj0 = j0 + (int64_t)c * kRedoChunk;
     const int64_t cj1 = cj0 + kRedoChunk < j1 ? cj0 + kRedoChunk : j1;
     double xi[kRedoRows], yi[kRedoRows], zi[kRedoRows], vxi[kRedoRows], vyi[kRedoRows],
@@ -612,17 +622,17 @@ __device__ __forceinline__ void redo_chunk_rows(const ForceArgs &a, int32_t q0, 
 #pragma unroll
     for (int r = 0; r < kRedoRows; ++r) {
         S[r].zero();
-        const int32_t q = q0 + (r < nr ? r : 0);
-        const int64_t b = a.redo_rows[q];
-        const int64_t i = a.i_block[b];
+        const int32_t q = q0 + (r < nr ? r : 0);   // uniform: scalar registers
+        const int64_t b = load_word_uniform(a.redo_rows + q);
+        const int64_t i = load_word_uniform(a.i_block + b);
         ii[r] = i;
-        xi[r] = a.xp[i];
-        yi[r] = a.xp[a.n + i];
-        zi[r] = a.xp[2 * a.n + i];
-        vxi[r] = a.vp[i];
-        vyi[r] = a.vp[a.n + i];
-        vzi[r] = a.vp[2 * a.n + i];
-        rs2f[r] = (float)a.rs2[b];
+        xi[r] = load_f64_uniform(a.xp + i);
+        yi[r] = load_f64_uniform(a.xp + a.n + i);
+        zi[r] = load_f64_uniform(a.xp + 2 * a.n + i);
+        vxi[r] = load_f64_uniform(a.vp + i);
+        vyi[r] = load_f64_uniform(a.vp + a.n + i);
+        vzi[r] = load_f64_uniform(a.vp + 2 * a.n + i);
+        rs2f[r] = (float)load_f64_uniform(a.rs2 + b);
         hi[r] = cand_bound_f64(rs2f[r]);
     }
     for (int64_t j = cj0 + threadIdx.x; j < cj1; j += kBlock) {

@@ -413,21 +413,23 @@ def _same_result(got, want, cap, what):
     check_lists(got[2], got[3], want[2], want[3], cap)
 
 
-@pytest.mark.parametrize("plan", [(0, 0, 0), (1, 1, 1), (1, 1, 6), (2, 1, 400)])
-def test_refinement_of_every_flagged_row(plan):
+@pytest.mark.parametrize("plan,rows", [((0, 0, 0), 300), ((1, 1, 1), 300), ((1, 1, 6), 300),
+                                       ((2, 1, 400), 300), ((0, 0, 0), 1500), ((1, 1, 6), 1500)])
+def test_refinement_of_every_flagged_row(plan, rows):
     """A mixed-precision tolerance so small that every row is flagged: every
-    row is recomputed in FP64 by the refinement launch (chunk partials, added
-    by the work-group that finishes last), so the mixed call meets the FP64
-    bar.  Calls in between that flag nothing, and repeated calls, leave the
-    refinement's arrival word ready: the flagged call gives the same bits
+    row is recomputed in FP64 by the refinement (chunk partials, added by the
+    work-group that finishes last in blocks of up to 1024 rows, by a launch of
+    their own, a wave per row, in larger ones), so the mixed call meets the
+    FP64 bar.  Calls in between that flag nothing, and repeated calls, leave
+    the refinement's arrival word ready: the flagged call gives the same bits
     every time.  Plans: automatic, one split (rows flagged by the force
     kernel), a few splits (lane-group merge), 313 splits (work-group merge)."""
-    say(f"refinement of every row, plan {plan}")
+    say(f"refinement of every row, plan {plan}, {rows} rows")
     c = nb.Context(0)
     try:
         n = 20000
         x, v, m = _uniform_cube(911, n)
-        ib = np.random.default_rng(912).choice(n, 300, replace=False).astype(np.int32)
+        ib = np.random.default_rng(912).choice(n, rows, replace=False).astype(np.int32)
         rs2 = np.full(ib.size, 0.08 ** 2)
         cap = 256
         X, V, M, IB, RS = dev(x), dev(v), dev(m), dev(ib), dev(rs2)
