@@ -46,12 +46,11 @@ FLOPS_PER_PAIR = 40
 ADJ_FLOPS_ROWS = 65
 ADJ_FLOPS_BODIES = 83
 
-# MI355X published vector peaks (TFLOP/s): FP32 157.3 (with packed FP32
-# instructions), FP64 78.6.  256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz =
-# 78.6 TFLOP/s is also the ceiling of unpacked FP32.
+# MI355X published vector peaks (TFLOP/s): FP32 157.3, FP64 78.6.  Plain
+# (unpacked) FP32 instructions issue in 2 cycles per wave64 on gfx950 and
+# FP64 ones in 4, which are these two rates on 256 CUs x 4 SIMDs at 2.4 GHz.
 PEAK_FP32 = 157.3
 PEAK_FP64 = 78.6
-PEAK_UNPACKED = 78.6
 
 
 def log(*a):
@@ -72,9 +71,10 @@ def kernel_src_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(prec: str):
-    """HBM bytes per launch of the full-block force kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that summary was
+def profiled(prec: str, key: str):
+    """A figure of the full-block force kernel from the committed rocprofv3
+    counter summary (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE, the
+    fraction of the instruction issue model), or None when that summary was
     taken on different kernel sources (or does not exist)."""
     path = os.path.join(ROOT, "profiles", "force_rows_kernel_full_block_n1048576.traffic.json")
     try:
@@ -84,7 +84,7 @@ def measured_traffic(prec: str):
         return None
     if d.get("kernel_src_sha1") != kernel_src_hash():
         return None
-    return d.get(prec, {}).get("hbm_bytes_per_launch")
+    return d.get(prec, {}).get(key)
 
 
 def steady_ms(call, warm_ms=30.0, time_ms=50.0, min_reps=3):
@@ -700,10 +700,10 @@ def main():
                    "n": n, "n_i": n_i, "pairs_per_step": pairs},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": measured_traffic(dom),
+                     "traffic": profiled(dom, "hbm_bytes_per_launch"),
                      "kernel": f"force_rows_kernel ({dom})",
                      "flops_per_pair": FLOPS_PER_PAIR,
-                     "frac_of_unpacked_fp32_fp64_peak": round(achieved / PEAK_UNPACKED, 4)},
+                     "issue_model_frac": profiled(dom, "issue_model_frac")},
         "cpu_baseline": cpu,
         "precisions": {p: {"gpairs_per_s": round(r["pairs_per_s"] * 1e-9, 3),
                            "ms_per_step": round(r["ms_per_step"], 3),
