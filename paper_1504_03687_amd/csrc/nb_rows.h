@@ -470,9 +470,27 @@ __device__ __forceinline__ void merge_row(const ForceArgs &a, int64_t b, bool ha
             const int64_t start = off + inc - c;
             const bool room = c > 0 && start < a.cap;
             const bool rebuild = room && c > kSegCap;
-            // segments that fit: the whole group copies each one (coalesced)
+            // segments that fit.  Short ones (at most kLaneCopy entries, the
+            // usual case with many splits): each lane copies its own in
+            // 16-byte loads (a segment's storage holds kSegCap entries, a
+            // multiple of 8, so the loads stay inside it), all segments of the
+            // group in flight together.  Longer ones: the whole group copies
+            // each in turn (coalesced).
+            static_assert(kSegCap % 8 == 0, "segment storage in 8-entry rounds");
+            constexpr int64_t kLaneCopy = 16;
             const int64_t take = room ? ((int64_t)c < a.cap - start ? c : a.cap - start) : 0;
-            uint64_t cp = __ballot(room && !rebuild) & gmask;
+            if (room && !rebuild && take <= kLaneCopy) {
+                const int4 *src = reinterpret_cast<const int4 *>(a.seg_list + slot * kSegCap);
+                int32_t *dst = a.nb_list + b * (int64_t)a.cap + start;
+                for (int64_t e = 0; e < take; e += 8) {
+                    const int4 u0 = src[e / 4], u1 = src[e / 4 + 1];
+                    const int32_t t[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if (e + k < take) dst[e + k] = t[k];
+                }
+            }
+            uint64_t cp = __ballot(room && !rebuild && take > kLaneCopy) & gmask;
             while (cp) {
                 const int q = __builtin_ctzll(cp);
                 cp &= cp - 1;
