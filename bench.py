@@ -468,6 +468,10 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only time the adjoint at N = 65536 (all active, FP64) and print "
                          "its figures (used for kernel profiles)")
+    ap.add_argument("--batched-profile", action="store_true",
+                    help="only replay the 256-cluster batched call three times in mixed "
+                         "precision at the (256, 512, 1) shape with 64 items per CU and three "
+                         "times in FP64 at the default shape (used for kernel profiles)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (FP64 elementwise kernel) "
                          "and print its bandwidth; used to scale rocprofv3 byte counters")
@@ -502,6 +506,23 @@ def main():
     if args.adjoint_only:
         ctx = nb.Context(0)
         print(json.dumps({"adjoint": adjoint_leg(nb, W, ctx, dev)}), flush=True)
+        return
+    if args.batched_profile:
+        ctx = nb.Context(0)
+        s4 = W.cluster_ensemble_256()
+        xp4, vp4, _ = nb.predict(dev(s4["x"]), dev(s4["v"]), dev(s4["a"]), dev(s4["jk"]),
+                                 dev(s4["t0"]), s4["t"], ctx=ctx)
+        b4 = (s4["j_off"], s4["i_off"], xp4, vp4, dev(s4["m"]), dev(s4["i_block"]),
+              dev(s4["rs2"]))
+        plans = {}
+        for prec, shape in (("mixed", (256, 512, 1, 64)), ("fp64", (0, 0, 0, 0))):
+            ctx.set_batched_shape(*shape)
+            o4 = nb.regular_force_batched(*b4, s4["nb_cap"], prec, ctx=ctx)
+            for _ in range(2):
+                nb.regular_force_batched(*b4, s4["nb_cap"], prec, out=o4, ctx=ctx)
+            torch.cuda.synchronize()
+            plans[prec] = ctx.last_plan()
+        print(json.dumps({"batched_profile": plans}), flush=True)
         return
     t_gen = time.time()
     s = W.binary_cluster_n1m(args.n)
