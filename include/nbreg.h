@@ -99,8 +99,9 @@ int nb_version(void);
  * automatically".  mapping: 1 = one row per lane with j-tiles in LDS
  * (256-lane work-groups), 2 = 1, 2 or 4 rows per wavefront with j spread
  * over lanes (the smallest blocks), 3 = one row per lane in one-wave
- * work-groups with 64-body LDS tiles (blocks of a few dozen to a few hundred
- * rows).  rows_per_lane: 1, 2 or 4 (mapping 1; rows per wave for mapping 2;
+ * work-groups with 64-body LDS tiles (automatic for blocks above 40 rows
+ * whose rows fill 64-row tiles more than 1.2 times better than 256-row
+ * ones, so at most 832 rows).  rows_per_lane: 1, 2 or 4 (mapping 1; rows per wave for mapping 2;
  * ignored by mapping 3).  splits: number of contiguous j ranges whose partial
  * sums are combined in FP64 (>= 1).  The override holds until changed; pass
  * all zeros to go back to automatic plans. */

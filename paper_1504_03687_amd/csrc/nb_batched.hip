@@ -28,7 +28,7 @@ namespace nb {
 namespace {
 
 template <bool MIXED, int IR, int T, int NB>
-__global__ __launch_bounds__(NB) void batched_kernel(BatchArgs A)
+__global__ __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(IR == 1 && T == 256 ? 4 : 1))) void batched_kernel(BatchArgs A)
 {
     __shared__ JBody tile[2][T];
     __shared__ int32_t s_item;

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void force_rows_kernel(ForceArgs a)
 // blocks of a few row tiles fill the lanes of 64-row groups instead of
 // leaving most of a 256-lane work-group idle.  grid = (ceil(n_i / 64), splits).
 template <bool MIXED>
-__global__ __launch_bounds__(kWave) void force_rows_wave_kernel(ForceArgs a)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void force_rows_wave_kernel(ForceArgs a)
 {
     __shared__ JBody tile[2][kWave];
     clear_call_words(a);

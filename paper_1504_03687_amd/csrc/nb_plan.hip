@@ -86,13 +86,17 @@ int64_t default_splits(const nb_ctx *ctx, int64_t n, int32_t n_i, int mapping, i
 //    kWaveMaxRows: 32 rows 67.6 us FP64, against 104.7 us with one-wave
 //    row-per-lane work-groups (half their lanes idle) and more than that with
 //    256-lane work-groups;
-//  * one-wave row-per-lane work-groups (mapping 3) up to kRowsWaveMaxRows:
-//    64 rows 95 / 110 us against 136 (wave), 128 rows 154 / 192 us against
-//    236, 192 rows 214 / 274 us against 232 (256-lane) / 338 (wave);
-//  * 256-lane row-per-lane work-groups above: 256 rows 302 / 349 us against
-//    319 / 355 with one-wave work-groups.
+//  * above that, one-wave row-per-lane work-groups (mapping 3) when the
+//    256-row tiles of mapping 1 would hold more than 1.2 times the rows of
+//    64-row tiles, else mapping 1.  Per filled lane mapping 1 is the faster
+//    one (256 rows 255 / 350 us against 268 / 362 with mapping 3, 512 rows
+//    512 / 669 against 559 / 714), so it needs a clear lane advantage:
+//    64 rows 87 us mixed against 136 (wave), 192 rows 207 / 276 against
+//    226 / 285, 320 rows 379 / 451 against 508 / 598, 832 rows 896 / 1179
+//    against 939 / 1268; at 448 rows (ratio 1.14) the two tie, at 640 (1.2)
+//    mapping 1 leads by 4%, at 1088 (1.18) by 21%.  The largest block this
+//    picks mapping 3 for is 832 rows.
 constexpr int32_t kWaveMaxRows = 40;
-constexpr int32_t kRowsWaveMaxRows = 192;
 
 // Largest block whose mixed-precision request runs the FP64 kernels in the
 // automatic plan: the wave mapping, which is bound by memory latency, so its
@@ -100,7 +104,7 @@ constexpr int32_t kRowsWaveMaxRows = 192;
 // launch (nor, for a flagged row, the refinement itself).  N = 2^20, mixed vs
 // FP64 wave kernels: 1 row 22.7 vs 20.4 us, 8 rows 36.7 vs 31.4, 32 rows
 // 124.7 (one row refined) vs 67.3.  From 64 rows up the mixed one-wave
-// row-per-lane kernel is ahead (95 against the FP64 wave kernel's 137 us).
+// row-per-lane kernel is ahead (87 against the FP64 wave kernel's 137 us).
 // The results of such a call meet the FP64 bar.
 constexpr int32_t kMixedAsF64MaxRows = kWaveMaxRows;
 
@@ -121,10 +125,10 @@ Plan auto_plan(const nb_ctx *ctx, int64_t n, int32_t n_i, bool mixed)
     if (n_i <= kWaveMaxRows) {
         p.mapping = 2;
         p.rows_per_lane = n_i >= 4 ? 4 : (n_i >= 2 ? 2 : 1);
-    } else if (n_i <= kRowsWaveMaxRows) {
-        p.mapping = 3;
     } else {
-        p.mapping = 1;
+        const int64_t pad1 = ((int64_t)n_i + nb::kBlock - 1) / nb::kBlock * nb::kBlock;
+        const int64_t pad3 = ((int64_t)n_i + nb::kWave - 1) / nb::kWave * nb::kWave;
+        p.mapping = pad1 * 5 > pad3 * 6 ? 3 : 1;
     }
     p.splits = (int)default_splits(ctx, n, n_i, p.mapping, p.rows_per_lane);
     return p;

@@ -524,8 +524,10 @@ def test_workgroup_merge_many_rows_and_row_independence(ctx, prec):
 def test_small_mixed_blocks_run_fp64_kernels(ctx):
     """Under automatic plans a mixed-precision request on a block of at most
     40 rows runs the FP64 kernels (latency-bound there) and meets the FP64
-    bar; 41 and 128 rows run the mixed kernels (one-wave row-per-lane
-    work-groups); a forced plan keeps the mixed kernels too."""
+    bar; 41, 128 and 320 rows run the mixed kernels in one-wave row-per-lane
+    work-groups (64-row tiles fill their lanes more than 1.2 times better
+    than 256-row ones), 193 and 640 rows in 256-lane ones; a forced plan
+    keeps the mixed kernels too."""
     say("small mixed blocks on FP64 kernels")
     n = 30000
     x, v, m = _uniform_cube(918, n)
@@ -533,7 +535,8 @@ def test_small_mixed_blocks_run_fp64_kernels(ctx):
     X, V, M = dev(x), dev(v), dev(m)
     for n_i, want in ((1, "prec=fp64 requested=mixed"), (40, "prec=fp64 requested=mixed"),
                       (41, "mapping=3 rows_per_lane=1"), (128, "mapping=3 rows_per_lane=1"),
-                      (193, "mapping=1 rows_per_lane=1")):
+                      (193, "mapping=1 rows_per_lane=1"), (320, "mapping=3 rows_per_lane=1"),
+                      (640, "mapping=1 rows_per_lane=1")):
         ib = rng.choice(n, n_i, replace=False).astype(np.int32)
         rs2 = np.full(n_i, 0.07 ** 2)
         res = nb.regular_force(X, V, M, dev(ib), dev(rs2), 128, "mixed", ctx=ctx)
