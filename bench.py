@@ -470,8 +470,8 @@ def main():
                          "its figures (used for kernel profiles)")
     ap.add_argument("--batched-profile", action="store_true",
                     help="only replay the 256-cluster batched call three times in mixed "
-                         "precision at the (256, 512, 1) shape with 64 items per CU and three "
-                         "times in FP64 at the default shape (used for kernel profiles)")
+                         "precision and three times in FP64, at the default shape (used for "
+                         "kernel profiles)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (FP64 elementwise kernel) "
                          "and print its bandwidth; used to scale rocprofv3 byte counters")
@@ -515,8 +515,7 @@ def main():
         b4 = (s4["j_off"], s4["i_off"], xp4, vp4, dev(s4["m"]), dev(s4["i_block"]),
               dev(s4["rs2"]))
         plans = {}
-        for prec, shape in (("mixed", (256, 512, 1, 64)), ("fp64", (0, 0, 0, 0))):
-            ctx.set_batched_shape(*shape)
+        for prec in ("mixed", "fp64"):
             o4 = nb.regular_force_batched(*b4, s4["nb_cap"], prec, ctx=ctx)
             for _ in range(2):
                 nb.regular_force_batched(*b4, s4["nb_cap"], prec, out=o4, ctx=ctx)
