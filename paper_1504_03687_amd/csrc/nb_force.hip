@@ -324,7 +324,7 @@ __device__ __forceinline__ void write_forces(const ForceArgs &a, int64_t b, cons
 // order (kFinalBatch of them loaded before any is added).  Starting from zero
 // in chunk order, this is the sum of the unbuffered route.  slot / slots: this
 // lane's row slot and the number of slots (rows q = slot, slot + slots, ...).
-constexpr int kFinalBatch = 16;
+constexpr int kFinalBatch = 32;
 constexpr int kFinalRowsPerGroup = kBlock / 6;
 
 __device__ __forceinline__ void redo_final_rows(const ForceArgs &a, int32_t par, int32_t slot,
