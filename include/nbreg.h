@@ -130,6 +130,12 @@ int nb_ctx_reset_timing(nb_ctx *ctx);
  * (forces only; lists are already exact).  Defaults: tol 5e-6, safety 32.
  * tol = 0 turns the refinement off. */
 int nb_ctx_set_mixed_tolerance(nb_ctx *ctx, double tol, double safety);
+/* Test override of the refinement's buffer: at most 'rows' refined rows of a
+ * single-block call (nb_regular_force, nb_regular_force_noalloc) keep chunk
+ * partials, summed by the whole GPU; the others are refined one work-group
+ * per row, chunk after chunk, to the same bits.  0 = automatic (as many rows
+ * as 2^20 chunk partials hold); rows < 0 is NB_ERR_INVALID_ARG. */
+int nb_ctx_set_refine_buffer_rows(nb_ctx *ctx, int32_t rows);
 /* Number of rows the last NB_MIXED nb_regular_force call recomputed in FP64
  * (0 if refinement was off).  Synchronises the context's stream. */
 int nb_ctx_last_refined_rows(nb_ctx *ctx, int32_t *rows);

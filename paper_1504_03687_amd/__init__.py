@@ -82,6 +82,7 @@ def lib() -> C.CDLL:
             "nb_ctx_kernel_time": ([vp, C.c_int, C.POINTER(dbl), C.POINTER(i64)], C.c_int),
             "nb_ctx_reset_timing": ([vp], C.c_int),
             "nb_ctx_set_mixed_tolerance": ([vp, dbl, dbl], C.c_int),
+            "nb_ctx_set_refine_buffer_rows": ([vp, C.c_int32], C.c_int),
             "nb_ctx_last_refined_rows": ([vp, C.POINTER(i32)], C.c_int),
             "nb_predict": ([vp, i64, dbl, vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
             "nb_regular_force": ([vp, i64, vp, vp, vp, i32, vp, vp, i32, C.c_int, vp, vp, vp,
@@ -219,6 +220,13 @@ class Context:
         (tol = 0: never)."""
         _check(lib().nb_ctx_set_mixed_tolerance(self._h, float(tol), float(safety)),
                "nb_ctx_set_mixed_tolerance")
+
+    def set_refine_buffer_rows(self, rows: int = 0):
+        """Test override: at most `rows` refined rows of a single-block call
+        keep chunk partials; the rest are refined one work-group per row, to
+        the same bits (0 = automatic)."""
+        _check(lib().nb_ctx_set_refine_buffer_rows(self._h, int(rows)),
+               "nb_ctx_set_refine_buffer_rows")
 
     def last_refined_rows(self) -> int:
         """Rows the last mixed call recomputed in FP64 (synchronises)."""

@@ -63,6 +63,7 @@ struct nb_ctx {
     // the rounding-error estimate that triggers an FP64 recompute (tol 0: off)
     double mixed_tol = 5e-6;
     double mixed_safety = 32.0;
+    int32_t redo_rows_limit = 0;   // refined rows with buffered partials (0: automatic)
     // timing
     bool timing = false;
     std::vector<nbrt::PendingTiming> pending;

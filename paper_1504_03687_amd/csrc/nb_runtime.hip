@@ -384,12 +384,12 @@ static int regular_force_impl(nb_ctx *ctx, int64_t n, const double *xp, const do
     fa.near_factor = n >= nb::kNearMinBodies ? nb::kNearFactor : 1.0f;
     const int32_t groups = nb::redo_groups_for(ctx->cu_count);
     void *base = nullptr;
-    int32_t rcap_limit = 0;
-    size_t redo_bytes = fa.redo_k > 0.0 ? nb::redo_scratch_bytes(n_i, n) : 0;
+    int32_t rcap_limit = ctx->redo_rows_limit;   // 0: automatic
+    size_t redo_bytes = fa.redo_k > 0.0 ? nb::redo_scratch_bytes(n_i, n, rcap_limit) : 0;
     if (fixed) {
         // the refinement's chunk partials shrink first (rows past them are
         // summed one work-group each, to the same bits), then the splits
-        for (rcap_limit = (int32_t)nb::kRedoPartItems;
+        for (rcap_limit = rcap_limit > 0 ? rcap_limit : (int32_t)nb::kRedoPartItems;
              redo_bytes > fixed_bytes / 2 && rcap_limit > 1; rcap_limit /= 2)
             redo_bytes = nb::redo_scratch_bytes(n_i, n, rcap_limit / 2);
         if (redo_bytes > fixed_bytes) return NB_ERR_TOO_LARGE;
@@ -492,6 +492,13 @@ int nb_ctx_set_mixed_tolerance(nb_ctx *ctx, double tol, double safety)
     if (!ctx || !(tol >= 0.0) || !(safety > 0.0)) return NB_ERR_INVALID_ARG;
     ctx->mixed_tol = tol;
     ctx->mixed_safety = safety;
+    return NB_OK;
+}
+
+int nb_ctx_set_refine_buffer_rows(nb_ctx *ctx, int32_t rows)
+{
+    if (!ctx || rows < 0) return NB_ERR_INVALID_ARG;
+    ctx->redo_rows_limit = rows;
     return NB_OK;
 }
 

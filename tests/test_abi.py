@@ -75,6 +75,9 @@ def test_argument_validation(host_ctx):
     assert L.nb_ctx_set_plan(host_ctx, 1, 2, 4) == 0
     assert L.nb_ctx_set_plan(host_ctx, 0, 0, 0) == 0
     assert L.nb_ctx_set_scratch_limit(host_ctx, -1) == E
+    assert L.nb_ctx_set_refine_buffer_rows(host_ctx, -1) == E
+    assert L.nb_ctx_set_refine_buffer_rows(host_ctx, 7) == 0
+    assert L.nb_ctx_set_refine_buffer_rows(host_ctx, 0) == 0
 
 
 def test_gpu_context_refused_without_gfx950():

@@ -452,6 +452,44 @@ def test_refinement_of_every_flagged_row(plan, rows):
         c.close()
 
 
+def test_refined_rows_independent_of_route():
+    """A refined row's FP64 result depends only on the row and its j-range:
+    rows refined in a 300-row call (pass 2 in the same launch), in a 1500-row
+    call that contains them (pass 2 in a launch of its own), and with the
+    partials buffer capped at 1 or 7 rows (the others refined one work-group
+    per row, chunk after chunk), in regular and allocation-free calls, are
+    the same bits."""
+    say("refined rows independent of route")
+    c = nb.Context(0)
+    try:
+        n = 20000
+        x, v, m = _uniform_cube(931, n)
+        rng = np.random.default_rng(932)
+        big = rng.choice(n, 1500, replace=False).astype(np.int32)
+        small = big[:300].copy()
+        X, V, M = dev(x), dev(v), dev(m)
+        rs_small, rs_big = dev(np.full(300, 0.08 ** 2)), dev(np.full(1500, 0.08 ** 2))
+        c.set_mixed_tolerance(1e-30, 32.0)
+        ref = nb.regular_force(X, V, M, dev(small), rs_small, 256, "mixed", ctx=c)
+        assert c.last_refined_rows() == 300
+        want = [host(ref[0]), host(ref[1])]
+        res = nb.regular_force(X, V, M, dev(big), rs_big, 256, "mixed", ctx=c)
+        assert c.last_refined_rows() == 1500
+        for k in (0, 1):
+            assert np.array_equal(host(res[k])[:, :300], want[k]), "fused vs separate final launch"
+        for cap in (1, 7):
+            c.set_refine_buffer_rows(cap)
+            res = nb.regular_force(X, V, M, dev(small), rs_small, 256, "mixed", ctx=c)
+            out = tuple(torch.empty_like(t) for t in res)
+            nb.regular_force_noalloc(X, V, M, dev(small), rs_small, 256, "mixed", out=out, ctx=c)
+            for k in (0, 1):
+                assert np.array_equal(host(res[k]), want[k]), f"buffer of {cap} rows"
+                assert np.array_equal(host(out[k]), want[k]), f"buffer of {cap} rows, no-alloc"
+        compare_force(ref, x, v, m, small, np.full(300, 0.08 ** 2), 256, TOL_FP64)
+    finally:
+        c.close()
+
+
 def test_graph_replay_of_small_blocks(ctx):
     """A stepping loop may capture its block calls in a graph: replays of a
     captured small-block call (split force launch, merge and refinement, no
