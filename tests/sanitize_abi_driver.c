@@ -59,6 +59,9 @@ int main(void)
     EXPECT(nb_ctx_set_mixed_tolerance(ctx, -1.0, 32.0), E);
     EXPECT(nb_ctx_set_mixed_tolerance(ctx, 5e-6, 0.0), E);
     EXPECT(nb_ctx_set_mixed_tolerance(ctx, 5e-6, 32.0), NB_OK);
+    EXPECT(nb_ctx_set_refine_buffer_rows(ctx, -1), E);
+    EXPECT(nb_ctx_set_refine_buffer_rows(ctx, 3), NB_OK);
+    EXPECT(nb_ctx_set_refine_buffer_rows(ctx, 0), NB_OK);
     int32_t refined = -1;
     EXPECT(nb_ctx_last_refined_rows(ctx, &refined), NB_OK);
     EXPECT(nb_ctx_last_refined_rows(ctx, NULL), E);
