@@ -27,6 +27,10 @@
 namespace nb {
 namespace {
 
+// The one-row shapes with 256-body tiles are held to four waves per SIMD
+// (the mixed 256-lane one needed 129 VGPRs, one too many: 21.9 ms per call
+// on the 256-cluster ensemble against 20.7 at 128, no spill); the other
+// shapes would spill.
 template <bool MIXED, int IR, int T, int NB>
 __global__ __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(IR == 1 && T == 256 ? 4 : 1))) void batched_kernel(BatchArgs A)
 {

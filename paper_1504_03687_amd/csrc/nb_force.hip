@@ -58,6 +58,9 @@ __global__ __launch_bounds__(kBlock) void force_rows_kernel(ForceArgs a)
 // One-wave work-groups of the row-per-lane pass (64 rows, a 64-body LDS tile):
 // blocks of a few row tiles fill the lanes of 64-row groups instead of
 // leaving most of a 256-lane work-group idle.  grid = (ceil(n_i / 64), splits).
+// Held to four waves per SIMD (128 VGPRs, no spill): the plan puts about 16
+// work-groups on each CU, and at the compiler's 130 VGPRs only 12 fit at
+// once (64 rows took 95 us instead of 87).
 template <bool MIXED>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void force_rows_wave_kernel(ForceArgs a)
 {
