@@ -153,14 +153,15 @@ def cpu_model() -> str:
 
 
 def small_blocks_leg(nb, ctx, dev, s, xp, vp, m, cap, precs):
-    """Blocks of 1, 32 and 1024 random rows of the 2^20 cluster (HBM- and
-    launch-bound), in steady state with outputs reused across calls, as in a
-    stepping loop: per call from the host (us) and replayed from a captured
-    graph (graph_us, the launch chain alone)."""
+    """Blocks of 1, 32, 1024 and 320 random rows of the 2^20 cluster (HBM-
+    and launch-bound; 320 rows run one-wave work-groups), in steady state with
+    outputs reused across calls, as in a stepping loop: per call from the host
+    (us) and replayed from a captured graph (graph_us, the launch chain
+    alone)."""
     n = s["n"]
     small = {}
     rng = np.random.default_rng(1)
-    for size in (1, 32, 1024):
+    for size in (1, 32, 1024, 320):
         sb = rng.choice(n, size, replace=False).astype(np.int32)
         bd, rd = dev(sb), dev(s["rs2"][sb])
         ent = {}
@@ -463,7 +464,7 @@ def main():
                     help="only time the block-step scheduler on the same cluster's levels "
                          "and print its figures (used for kernel profiles)")
     ap.add_argument("--small-only", action="store_true",
-                    help="only time the small blocks (1, 32, 1024 random rows of the 2^20 "
+                    help="only time the small blocks (1, 32, 1024, 320 random rows of the 2^20 "
                          "cluster) and print their figures (used for kernel profiles)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only time the adjoint at N = 65536 (all active, FP64) and print "
